@@ -1,0 +1,287 @@
+/*
+ * srot_oracle.c -- plain FP64 CPU oracle for block-coordinate Frank-Wolfe
+ * (BCFW) on the quadratic semi-relaxed optimal-transport problem
+ * (Fukunaga & Kasai, arXiv:2103.05857).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the GPU library; it is deliberately slow and written so that every
+ * routine can be checked against the paper by eye.
+ *
+ * Orientation.  The paper keeps the column sums of T exact and relaxes the
+ * row sums.  This oracle uses the transposed labelling: T is m x n,
+ * row sums are exact (T 1_n = a), each block is a row t_i in a_i * simplex,
+ * and the relaxed marginal is the column sum with residual
+ *     r = T^T 1_m - b                     (length n).
+ * The penalty weight w plays the role of the paper's 1/lambda, so the
+ * objective (eq. EuculideanSquareRelaxedProblem, Sec. 3) reads
+ *     f(T) = <T, C> + (w/2) ||T^T 1_m - b||^2 .
+ *
+ * All arithmetic is IEEE double; loops run in natural index order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* -------------------------------------------------------------------------
+ * Problem description.  Either C is given (row-major m x n, already widened
+ * to double by the caller), or the cost is the squared Euclidean distance
+ * between 3-D points X (m x 3) and Y (n x 3) stored as float, evaluated in
+ * double (cost model of Sec. 5.1; squared as in the barycentric projection,
+ * eq. barycentric_projection).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t m, n;
+    const double *C;   /* m*n row-major, or NULL when X,Y are used */
+    const float *X;    /* m*3 source points */
+    const float *Y;    /* n*3 target points */
+    const double *a;   /* m  exact row sums  */
+    const double *b;   /* n  relaxed column-sum target */
+    double w;          /* penalty weight, the paper's 1/lambda */
+} or_problem;
+
+/* Cost c_ij: stored entry, or squared Euclidean distance in double. */
+double or_cost(const or_problem *P, int64_t i, int64_t j)
+{
+    if (P->C) return P->C[i * P->n + j];
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double diff = (double)P->X[i * 3 + d] - (double)P->Y[j * 3 + d];
+        s += diff * diff;
+    }
+    return s;
+}
+
+/* Materialise the whole cost matrix (for tests on small sizes). */
+void or_cost_matrix(const or_problem *P, double *out)
+{
+    for (int64_t i = 0; i < P->m; ++i)
+        for (int64_t j = 0; j < P->n; ++j)
+            out[i * P->n + j] = or_cost(P, i, j);
+}
+
+/* Residual of the relaxed marginal, r = T^T 1_m - b, recomputed from T
+ * (the quantity inside the penalty of eq. EuculideanSquareRelaxedProblem). */
+void or_residual(const or_problem *P, const double *T, double *r)
+{
+    for (int64_t j = 0; j < P->n; ++j) r[j] = 0.0;
+    for (int64_t i = 0; i < P->m; ++i)
+        for (int64_t j = 0; j < P->n; ++j) r[j] += T[i * P->n + j];
+    for (int64_t j = 0; j < P->n; ++j) r[j] -= P->b[j];
+}
+
+/* Objective f(T) = <T,C> + (w/2)||T^T 1 - b||^2
+ * (eq. EuculideanSquareRelaxedProblem, Sec. 3).  r_out may be NULL. */
+double or_objective(const or_problem *P, const double *T, double *r_out)
+{
+    double *r = (double *)malloc(sizeof(double) * (size_t)P->n);
+    or_residual(P, T, r);
+    double lin = 0.0;
+    for (int64_t i = 0; i < P->m; ++i)
+        for (int64_t j = 0; j < P->n; ++j) lin += T[i * P->n + j] * or_cost(P, i, j);
+    double pen = 0.0;
+    for (int64_t j = 0; j < P->n; ++j) pen += r[j] * r[j];
+    if (r_out) memcpy(r_out, r, sizeof(double) * (size_t)P->n);
+    free(r);
+    return lin + 0.5 * P->w * pen;
+}
+
+/* Gradient of f with respect to block i (eq. RelaxedGradient, Sec. 3.1):
+ *     grad_i f = c_i + w * r ,  the same penalty part for every block. */
+void or_block_gradient(const or_problem *P, const double *r, int64_t i, double *grad)
+{
+    for (int64_t j = 0; j < P->n; ++j) grad[j] = or_cost(P, i, j) + P->w * r[j];
+}
+
+/* Linear minimisation oracle on a_i * simplex
+ * (eq. SemiRelaxedSubproblemImplement, Sec. 3.1): the minimising vertex is
+ * a_i e_j with j the index of the smallest gradient entry.  Ties go to the
+ * lowest index.  *margin receives (second smallest) - (smallest), the
+ * distance to the nearest competing vertex (+inf when n == 1). */
+int64_t or_lmo(int64_t n, const double *grad, double *margin)
+{
+    int64_t best = 0;
+    for (int64_t j = 1; j < n; ++j)
+        if (grad[j] < grad[best]) best = j;
+    double second = INFINITY;
+    for (int64_t j = 0; j < n; ++j)
+        if (j != best && grad[j] < second) second = grad[j];
+    if (margin) *margin = second - grad[best];
+    return best;
+}
+
+/* Decay step of Alg. 1 (Sec. 3.1), with m blocks and the global block-step
+ * counter k starting at 0:  gamma = 2m / (k + 2m). */
+double or_step_dec(int64_t k, int64_t m)
+{
+    return (2.0 * (double)m) / ((double)k + 2.0 * (double)m);
+}
+
+/* Exact line search for one block (eq. SemiRelaxedBCFWStep, Sec. 3.1), in
+ * the penalty-weight form: with d = t_i - s_i,
+ *     gamma = [ <d, c_i> + w <d, r> ] / ( w ||d||^2 ),
+ * restricted to [0, 1] (the step range stated in Sec. 3.1).  When the
+ * denominator vanishes (w == 0 or d == 0) the objective is linear along the
+ * segment: take the far end if it decreases, else stay. */
+double or_step_els(const or_problem *P, const double *t_i, const double *s_i,
+                   int64_t i, const double *r)
+{
+    double num = 0.0, dd = 0.0;
+    for (int64_t j = 0; j < P->n; ++j) {
+        double d = t_i[j] - s_i[j];
+        num += d * or_cost(P, i, j) + P->w * d * r[j];
+        dd += d * d;
+    }
+    double den = P->w * dd;
+    if (!(num > 0.0)) return 0.0;
+    if (den == 0.0 || num >= den) return 1.0;
+    return num / den;
+}
+
+/* Duality gap and certificates at a fixed plan T (Sec. 3.2.2).
+ *   G_i    = min_j (grad_i f)_j, attained at jstar_i (lowest index)
+ *   S      = the all-block LMO solution, s_i = a_i e_{jstar_i}
+ *   g_i    = <t_i - s_i, c_i> + w <t_i - s_i, r>          (eq. AppenEq:Gi)
+ *   g      = <T - S, C> + w <(T - S)^T 1, r>               (Thm 2)
+ *   f      = objective
+ *   D      = f - sum_i <t_i, grad_i f> + sum_i a_i G_i     (Lagrangian dual
+ *            of App. D; the minimum over each block is the one written in
+ *            the appendix derivation).
+ * Any of G, jstar, grow may be NULL.  out3 = {g, f, D}. */
+void or_gap(const or_problem *P, const double *T, double *G, int64_t *jstar,
+            double *grow, double *out3)
+{
+    const int64_t m = P->m, n = P->n;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *grad = (double *)malloc(sizeof(double) * (size_t)n);
+    double *S = (double *)calloc((size_t)(m * n), sizeof(double));
+    double f = or_objective(P, T, r);
+
+    /* all-block LMO */
+    double sum_t_grad = 0.0, sum_a_min = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        or_block_gradient(P, r, i, grad);
+        int64_t js = or_lmo(n, grad, NULL);
+        S[i * n + js] = P->a[i];
+        if (G) G[i] = grad[js];
+        if (jstar) jstar[i] = js;
+        for (int64_t j = 0; j < n; ++j) sum_t_grad += T[i * n + j] * grad[j];
+        sum_a_min += P->a[i] * grad[js];
+        if (grow) {
+            double gi = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                double d = T[i * n + j] - S[i * n + j];
+                gi += d * or_cost(P, i, j) + P->w * d * r[j];
+            }
+            grow[i] = gi;
+        }
+    }
+    /* Thm 2: g = <T - S, C> + w <(T - S)^T 1, r> */
+    double lin = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) lin += (T[i * n + j] - S[i * n + j]) * or_cost(P, i, j);
+    double pen = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double col = 0.0;
+        for (int64_t i = 0; i < m; ++i) col += T[i * n + j] - S[i * n + j];
+        pen += col * r[j];
+    }
+    out3[0] = lin + P->w * pen;
+    out3[1] = f;
+    out3[2] = f - sum_t_grad + sum_a_min;
+    free(r); free(grad); free(S);
+}
+
+/* Initial plan used by the paper's experiments and by Thm 1: every block
+ * at its first vertex, t_i = a_i e_1 (Sec. 5; Thm 1).  Zero-based: column 0. */
+void or_init_plan(const or_problem *P, double *T)
+{
+    memset(T, 0, sizeof(double) * (size_t)(P->m * P->n));
+    for (int64_t i = 0; i < P->m; ++i) T[i * P->n] = P->a[i];
+}
+
+/* BCFW block steps (Alg. 1, Sec. 3.1).  For each of nsteps iterations:
+ * take the block index given for this iteration (the random draw is an
+ * input), form the block gradient, solve the LMO, choose the step (ELS or
+ * decay), move t_i toward s_i, and carry the relaxed marginal along.
+ * T (m x n) and r (= T^T 1 - b) are updated in place; *k is the global
+ * block-step counter used by the decay rule.  Per-step traces may be NULL.
+ * rule: 0 = exact line search, 1 = decay.  Returns 0, or -1 on a bad index. */
+int or_bcfw_steps(const or_problem *P, double *T, double *r, int64_t *k,
+                  int rule, int64_t nsteps, const int32_t *idx,
+                  int32_t *tr_j, double *tr_gamma, double *tr_margin)
+{
+    const int64_t m = P->m, n = P->n;
+    double *grad = (double *)malloc(sizeof(double) * (size_t)n);
+    double *s = (double *)malloc(sizeof(double) * (size_t)n);
+    double *old = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t st = 0; st < nsteps; ++st) {
+        int64_t i = idx[st];
+        if (i < 0 || i >= m) { free(grad); free(s); free(old); return -1; }
+        double *t_i = T + i * n;
+        /* gradient of the selected block and its LMO vertex */
+        or_block_gradient(P, r, i, grad);
+        double margin;
+        int64_t js = or_lmo(n, grad, &margin);
+        for (int64_t j = 0; j < n; ++j) s[j] = 0.0;
+        s[js] = P->a[i];
+        /* step size */
+        double gamma = (rule == 1) ? or_step_dec(*k, m) : or_step_els(P, t_i, s, i, r);
+        /* block update t_i <- (1-gamma) t_i + gamma s_i; all other blocks kept */
+        for (int64_t j = 0; j < n; ++j) old[j] = t_i[j];
+        for (int64_t j = 0; j < n; ++j) t_i[j] = (1.0 - gamma) * t_i[j] + gamma * s[j];
+        /* the column sums change only through the updated block */
+        for (int64_t j = 0; j < n; ++j) r[j] += t_i[j] - old[j];
+        if (tr_j) tr_j[st] = (int32_t)js;
+        if (tr_gamma) tr_gamma[st] = gamma;
+        if (tr_margin) tr_margin[st] = margin;
+        *k += 1;
+    }
+    free(grad); free(s); free(old);
+    return 0;
+}
+
+/* Full Frank-Wolfe iteration (Alg. A.1, App. A): LMO on every block, then
+ * one step on the whole plan.  ELS per eq. AppenEq:SemiRelaxedFWStep in the
+ * penalty-weight form, with D = T - S:
+ *     gamma = [ <D, C> + w <D^T 1, r> ] / ( w ||D^T 1||^2 ),  in [0, 1];
+ * decay rule gamma = 2/(k+2).  Returns the gap g(T) measured before the
+ * step (the stopping quantity of Alg. A.1); *gamma_out receives the step. */
+double or_fw_iteration(const or_problem *P, double *T, int64_t k, int rule,
+                       double *gamma_out)
+{
+    const int64_t m = P->m, n = P->n;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *grad = (double *)malloc(sizeof(double) * (size_t)n);
+    double *S = (double *)calloc((size_t)(m * n), sizeof(double));
+    or_residual(P, T, r);
+    for (int64_t i = 0; i < m; ++i) {
+        or_block_gradient(P, r, i, grad);
+        S[i * n + or_lmo(n, grad, NULL)] = P->a[i];
+    }
+    double lin = 0.0, pen = 0.0, dd = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) lin += (T[i * n + j] - S[i * n + j]) * or_cost(P, i, j);
+    for (int64_t j = 0; j < n; ++j) {
+        double col = 0.0;
+        for (int64_t i = 0; i < m; ++i) col += T[i * n + j] - S[i * n + j];
+        pen += col * r[j];
+        dd += col * col;
+    }
+    double num = lin + P->w * pen;
+    double gamma;
+    if (rule == 1) {
+        gamma = 2.0 / ((double)k + 2.0);
+    } else {
+        double den = P->w * dd;
+        if (!(num > 0.0)) gamma = 0.0;
+        else if (den == 0.0 || num >= den) gamma = 1.0;
+        else gamma = num / den;
+    }
+    for (int64_t q = 0; q < m * n; ++q) T[q] = (1.0 - gamma) * T[q] + gamma * S[q];
+    if (gamma_out) *gamma_out = gamma;
+    free(r); free(grad); free(S);
+    return num;
+}
