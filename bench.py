@@ -1,0 +1,154 @@
+"""Benchmark of the BCFW hot path on one MI355X.
+
+Workload: m = n = 4096 points from the seeded 8-Gaussian RGB mixture, cost
+stored in FP32 (64 MiB), uniform a, b, penalty weights w in {0.1, 1, 10},
+ELS step, uniform sampling.  One benchmark "step" is one pass of the hot
+path: m block updates (sample, gradient row, LMO, line search, update of t_i
+and r) followed by the gap sweep and the stop test read back on the host.
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: block-updates/s over the timed passes (all three w),
+the chain kernel's roofline figures, the time to reach gap 1e-6 from the
+initial plan for each w, and the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed passes per penalty weight")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed passes per penalty weight")
+    ap.add_argument("--m", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--weights", type=str, default="0.1,1,10")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solves")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the BCFW chain does not shard across GPUs); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2103_05857_amd import inputs as I
+    from paper_2103_05857_amd import srot as S
+
+    dev = torch.device("cuda:0")
+    m, n = args.m, args.n
+    weights = [float(x) for x in args.weights.split(",")]
+    d = I.problem_mixture(0, m, n, cost_dtype=np.float32)
+    C = torch.from_numpy(d["C"]).to(dev)
+    a = torch.from_numpy(d["a"]).to(dev)
+    b = torch.from_numpy(d["b"]).to(dev)
+    torch.cuda.synchronize()
+
+    total_updates = 0
+    total_s = 0.0
+    chain_ms = []          # event-timed srot_step(m) launches (sample + chain kernel)
+    nnz_rows = []
+    ttg = {}
+    for w in weights:
+        sol = S.Solver(a, b, C=C, w=w, seed=0, eps=1e-6, max_passes=1, gap_every=1)
+        stream = torch.cuda.current_stream()
+        for _ in range(args.warmup):
+            S.srot_step(sol.h, m)
+            S.srot_gap(sol.h)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for p in range(args.steps):
+            ev[p][0].record(stream)
+            S.srot_step(sol.h, m)            # one pass of m block updates
+            ev[p][1].record(stream)
+            S.srot_gap(sol.h)                # gap sweep + stop-test readback (syncs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total_updates += args.steps * m
+        total_s += dt
+        chain_ms += [e0.elapsed_time(e1) for e0, e1 in ev]
+        T, _ = sol.plan()
+        nnz_rows.append(float((T > 0).sum().item()) / m)
+        sol.close()
+        del T
+        if not args.no_ttg:
+            sol = S.Solver(a, b, C=C, w=w, seed=0, eps=1e-6, max_passes=5000, gap_every=1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            status, (g, f, D), passes = sol.solve()
+            torch.cuda.synchronize()
+            ttg[str(w)] = dict(seconds=time.perf_counter() - t1, passes=passes, gap=g, f=f,
+                               converged=(status == S.SROT_OK))
+            sol.close()
+
+    value = total_updates / total_s
+    ms_per_step = 1000.0 * total_s / (args.steps * len(weights))
+    chain_avg_ms = float(np.mean(chain_ms))
+    # algorithmic bytes per block step: the FP32 cost row (4n) plus the sparse
+    # plan row read and written (int32 index + FP64 value, nnz + 1 entries)
+    nnz = float(np.mean(nnz_rows))
+    bytes_per_step = 4.0 * n + 24.0 * (nnz + 1.0)
+    achieved = bytes_per_step * m / (chain_avg_ms * 1e-3) / 1e9
+    roofline = dict(kernel="chain_reg_kernel<256,16,f32>", bound="hbm", achieved=achieved,
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    bytes_per_launch=bytes_per_step * m, launch_ms=chain_avg_ms,
+                    us_per_block_update=1000.0 * chain_avg_ms / m)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(d, m, weights[min(1, len(weights) - 1)], args.cpu_seconds)
+
+    out = {
+        "metric": "BCFW block-updates/sec (stored FP32 C, ELS, uniform sampling)",
+        "value": value, "unit": "block-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (FP32-stored cost)", "data": "synthetic",
+        "config": {"workload": f"bcfw_stored_f32_mixture_m{m}_n{n}", "m": m, "n": n,
+                   "weights": weights, "cost": "squared Euclidean, stored FP32",
+                   "step": "one pass = m block updates + gap sweep + stop test"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "time_to_gap_1e-6": ttg,
+        "mean_row_nnz": nnz,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(d, m, w, seconds):
+    """FP64 oracle, single thread, on the same workload: whole passes (m block
+    steps + gap) until about `seconds` of CPU time, extrapolated per update."""
+    from oracle import oracle as O
+    from paper_2103_05857_amd import inputs as I
+    P = O.Problem(d["a"], d["b"], w, C=d["C"].astype(np.float64))
+    st = O.State(P)
+    t0 = time.perf_counter()
+    passes = 0
+    while time.perf_counter() - t0 < seconds and passes < 1000:
+        O.bcfw_steps(P, st, I.philox_uniform_indices(0, passes * m, m, m), trace=False)
+        O.gap(P, st.T)
+        passes += 1
+    dt = time.perf_counter() - t0
+    return dict(value=passes * m / dt, unit="block-updates/s", cores=1, kind="oracle",
+                sample=f"{passes} passes (m={m} block steps + gap sweep each) at w={w}, "
+                       f"{dt:.1f} s, single-threaded FP64 C oracle")
+
+
+if __name__ == "__main__":
+    main()

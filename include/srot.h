@@ -1,0 +1,164 @@
+/*
+ * srot.h -- C ABI of the MI355X (gfx950) block-coordinate Frank-Wolfe solver
+ * for quadratic semi-relaxed optimal transport
+ * (Fukunaga & Kasai, arXiv:2103.05857).
+ *
+ * Problem (eq. EuculideanSquareRelaxedProblem, Sec. 3, written with blocks as
+ * rows): given a cost C (m x n), exact row sums a (m) and a target b (n) for
+ * the relaxed column sums,
+ *
+ *     minimise  f(T) = <T, C> + (w/2) || T^T 1_m - b ||^2
+ *     over      T >= 0,  T 1_n = a          (a product of scaled simplices,
+ *                                            eq. EuclideanRelaxedCartesian)
+ *
+ * w is the penalty weight (the paper's 1/lambda).  Each row t_i is one block
+ * of the block-coordinate method (Alg. 1, Sec. 3.1); r = T^T 1 - b is the
+ * residual of the relaxed marginal, kept on the device and updated in place.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" are HIP device pointers, "host" are host
+ *     pointers.  The caller owns every buffer it passes and keeps it alive
+ *     until srot_destroy; the library allocates no device memory: all its
+ *     state lives in the caller's workspace.
+ *   - Matrices are row-major and dense, rows contiguous (leading dim = n).
+ *   - All work is enqueued on the stream given to srot_init.  Entry points
+ *     that return host scalars (srot_gap, srot_solve) synchronise that
+ *     stream; the others return as soon as the work is enqueued.
+ *   - Return value: SROT_OK (0), SROT_NOT_CONVERGED (> 0, soft), or a
+ *     negative error code.  On error, srot_last_error() holds a message
+ *     (per thread).  No C++ exception crosses this interface.
+ *   - A handle is not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef SROT_H
+#define SROT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SROT_OK              0
+#define SROT_NOT_CONVERGED   1   /* max_passes reached with gap > eps   */
+#define SROT_EINVAL         -1   /* bad argument (shape, pointer, option) */
+#define SROT_ENOMEM         -2   /* workspace smaller than srot_workspace_size */
+#define SROT_ENONFINITE     -3   /* NaN/Inf or negative weight in the inputs  */
+#define SROT_EHIP           -4   /* a HIP runtime call failed                  */
+
+/* step rules (Alg. 1, Sec. 3.1) */
+#define SROT_ELS  0   /* exact line search, eq. SemiRelaxedBCFWStep     */
+#define SROT_DEC  1   /* decay step 2m/(k+2m), k = global block-step count */
+
+/* block sampling (Sec. 3.1) */
+#define SROT_UNIFORM  0   /* i.i.d. uniform rows (BCFW-U)             */
+#define SROT_PERMUTE  1   /* a fresh random permutation per pass (BCFW-P) */
+
+/* cost storage */
+#define SROT_COST_F32      0   /* C stored as float  (m x n)                 */
+#define SROT_COST_F64      1   /* C stored as double (m x n)                 */
+#define SROT_COST_SQEUCLID 2   /* C never stored: c_ij = ||x_i - y_j||^2 from
+                                  float points X (m x 3), Y (n x 3), evaluated
+                                  in double (Sec. 5.1 cost, squared)         */
+
+typedef struct srot_handle srot_handle;   /* opaque */
+
+typedef struct {
+    double   w;           /* penalty weight, >= 0 (the paper's 1/lambda)       */
+    int32_t  step_rule;   /* SROT_ELS | SROT_DEC                               */
+    int32_t  sampling;    /* SROT_UNIFORM | SROT_PERMUTE                       */
+    uint64_t seed;        /* key of the Philox4x64-10 block-index stream       */
+    double   eps;         /* stop when the duality gap g(T) <= eps (Sec. 3.1)  */
+    int64_t  max_passes;  /* passes of m block steps before giving up          */
+    int32_t  gap_every;   /* passes between gap evaluations (>= 1; the paper
+                             measures the gap once per pass, Sec. 3.1)         */
+    int32_t  cost;        /* SROT_COST_F32 | SROT_COST_F64 | SROT_COST_SQEUCLID */
+} srot_options;
+
+/* Fills *opt with: w = 1, ELS, uniform sampling, seed 0, eps = 1e-6,
+ * max_passes = 1000 (the paper's default budget of 1000 epochs, Sec. 5),
+ * gap_every = 1, cost = SROT_COST_F32. */
+void srot_default_options(srot_options *opt);
+
+/* Bytes of device workspace needed for an m x n problem with these options
+ * (dense FP64 plan, residual, index and reduction buffers; 256-byte aligned
+ * sub-buffers).  Returns 0 for invalid sizes. */
+size_t srot_workspace_size(int64_t m, int64_t n, const srot_options *opt);
+
+/* Creates a solver for one problem and sets the initial plan used by the
+ * paper's experiments and Thm 1: every row at its first vertex,
+ * t_i = a_i e_0, with the residual r computed from it; k = 0.
+ *   C         device; m x n float or double (opt->cost), or NULL for
+ *             SROT_COST_SQEUCLID.  Read at every step; must stay unchanged.
+ *   X, Y      device; m x 3 and n x 3 float.  Required for SROT_COST_SQEUCLID
+ *             and by srot_backward for point gradients; otherwise may be NULL.
+ *   a, b      device; m and n doubles, finite and >= 0.
+ *   workspace device; at least srot_workspace_size(m, n, opt) bytes, 256-byte
+ *             aligned.  Owned by the caller, used exclusively by this handle.
+ *   opt       host; copied.
+ *   stream    a hipStream_t (NULL = the default stream).
+ * Validates the inputs on the device (SROT_ENONFINITE on NaN/Inf anywhere in
+ * C/X/Y/a/b or a negative weight) and synchronises once.
+ * Errors: SROT_EINVAL (m, n < 1, m or n > 2^31 - 1, bad option, NULL pointer
+ * where one is required), SROT_ENOMEM, SROT_ENONFINITE, SROT_EHIP. */
+int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C,
+              const float *X, const float *Y, const double *a, const double *b,
+              void *workspace, size_t ws_bytes, const srot_options *opt,
+              void *stream);
+
+/* Runs nsteps BCFW block steps (Alg. 1): for each step take block i, form the
+ * block gradient c_i + w r (eq. RelaxedGradient), pick the LMO vertex
+ * a_i e_j* with j* the lowest index of the smallest gradient entry
+ * (eq. SemiRelaxedSubproblemImplement), take the ELS step
+ * (eq. SemiRelaxedBCFWStep, clipped to [0,1]) or the decay step, and update
+ * t_i and r in place.
+ *   idx          device, nsteps int32 block indices in [0, m), or NULL to draw
+ *                them from the handle's Philox stream (opt->sampling, seed)
+ *                at the handle's step counter.  Out-of-range indices give
+ *                SROT_EINVAL (checked on the device before any update).
+ *   trace_j      device, nsteps int32 (optional): the LMO vertex j* per step.
+ *   trace_gamma  device, nsteps double (optional): the step size per step.
+ * Enqueues the work and returns (one validation synchronisation when idx is
+ * given by the caller). */
+int srot_step(srot_handle *h, int64_t nsteps, const int32_t *idx,
+              int32_t *trace_j, double *trace_gamma);
+
+/* Duality gap at the current plan (Thm 2, Sec. 3.2.2) with its certificates:
+ *   out3[0] = g(T) = sum_i g_i,  g_i = <t_i - s_i, c_i + w r>  (eq. AppenEq:Gi)
+ *   out3[1] = f(T)
+ *   out3[2] = D(T), the Lagrangian dual value of App. D, = f - g
+ * out3 is host memory.  row_gap (device, m doubles) and row_argmin (device,
+ * m int32) are optional per-row outputs g_i and j*_i.  Synchronises. */
+int srot_gap(srot_handle *h, double *out3, double *row_gap, int32_t *row_argmin);
+
+/* Runs passes of m block steps, measuring the gap every opt->gap_every passes
+ * and stopping at the first measurement with g <= opt->eps, or after
+ * opt->max_passes passes (Sec. 3.1 stopping rule).
+ *   out3    host, {g, f, D} at the last measurement.
+ *   passes  host, number of passes run by this call.
+ * Returns SROT_OK when converged, SROT_NOT_CONVERGED otherwise. */
+int srot_solve(srot_handle *h, double *out3, int64_t *passes);
+
+/* Copies the dense plan T (device, m x n double) and the residual
+ * r = T^T 1 - b (device, n double) out; either may be NULL. */
+int srot_get_plan(srot_handle *h, double *T_out, double *r_out);
+
+/* Checkpoint / resume: the state is (T, r, k).  srot_get_state writes the
+ * block-step counter to *k (host).  srot_set_state loads a plan T (device,
+ * m x n double, rows must lie on a_i * simplex up to rounding; not checked),
+ * recomputes r from it and sets the counter to k.  With the counter-based
+ * block-index stream a resumed run repeats the uninterrupted one. */
+int srot_get_state(srot_handle *h, int64_t *k);
+int srot_set_state(srot_handle *h, const double *T_in, int64_t k);
+
+/* Destroys the handle (host memory only; the caller frees its buffers). */
+void srot_destroy(srot_handle *h);
+
+const char *srot_strerror(int status);
+const char *srot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SROT_H */

@@ -55,7 +55,7 @@ def _load():
     lib.or_gap.argtypes = [P, _dp, _dp, _i64p, _dp, _dp]
     lib.or_init_plan.argtypes = [P, _dp]
     lib.or_bcfw_steps.argtypes = [P, _dp, _dp, _i64p, ctypes.c_int, ctypes.c_int64,
-                                  _i32p, _i32p, _dp, _dp]
+                                  _i32p, _i32p, _dp, _dp, _i32p, _i32p, ctypes.c_double]
     lib.or_bcfw_steps.restype = ctypes.c_int
     lib.or_fw_iteration.argtypes = [P, _dp, ctypes.c_int64, ctypes.c_int, _dp]
     lib.or_fw_iteration.restype = ctypes.c_double
@@ -168,24 +168,38 @@ class State:
         self.k = 0
 
 
-def bcfw_steps(P, state, idx, rule=ELS, trace=True):
+class Trace(tuple):
+    """(jstar, gamma, margin) per step, plus .runner (the runner-up vertex)
+    and .near (steps x 4: columns within near_tol of the minimum, -1 padded)."""
+
+
+def bcfw_steps(P, state, idx, rule=ELS, trace=True, near_tol=1e-12):
     """Runs len(idx) BCFW block steps (Alg. 1) in place on state.
 
-    Returns (jstar, gamma, margin) traces (numpy arrays) when trace is set."""
+    Returns (jstar, gamma, margin) traces (numpy arrays) when trace is set; the
+    returned tuple also carries .runner and .near (see Trace)."""
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     ns = idx.shape[0]
     tj = np.empty(ns, dtype=np.int32) if trace else None
     tg = np.empty(ns, dtype=np.float64) if trace else None
     tm = np.empty(ns, dtype=np.float64) if trace else None
+    tr = np.empty(ns, dtype=np.int32) if trace else None
+    tn = np.empty((ns, 4), dtype=np.int32) if trace else None
     k = ctypes.c_int64(state.k)
     rc = _load().or_bcfw_steps(P.ref, _ptr(state.T, ctypes.c_double), _ptr(state.r, ctypes.c_double),
                                ctypes.byref(k), int(rule), ns, _ptr(idx, ctypes.c_int32),
                                _ptr(tj, ctypes.c_int32), _ptr(tg, ctypes.c_double),
-                               _ptr(tm, ctypes.c_double))
+                               _ptr(tm, ctypes.c_double), _ptr(tr, ctypes.c_int32),
+                               _ptr(tn, ctypes.c_int32), float(near_tol))
     if rc != 0:
         raise ValueError("block index out of range")
     state.k = k.value
-    return (tj, tg, tm) if trace else None
+    if not trace:
+        return None
+    out = Trace((tj, tg, tm))
+    out.runner = tr
+    out.near = tn
+    return out
 
 
 def solve(P, index_source, rule=ELS, eps=0.0, max_passes=1, gap_every=1, state=None,
@@ -211,10 +225,12 @@ def solve(P, index_source, rule=ELS, eps=0.0, max_passes=1, gap_every=1, state=N
             if gp["g"] <= eps:
                 break
     if trace:
-        tj = np.concatenate([t[0] for t in traces])
-        tg = np.concatenate([t[1] for t in traces])
-        tm = np.concatenate([t[2] for t in traces])
-        return st, hist, (tj, tg, tm)
+        out = Trace((np.concatenate([t[0] for t in traces]),
+                     np.concatenate([t[1] for t in traces]),
+                     np.concatenate([t[2] for t in traces])))
+        out.runner = np.concatenate([t.runner for t in traces])
+        out.near = np.concatenate([t.near for t in traces])
+        return st, hist, out
     return st, hist
 
 

@@ -99,17 +99,25 @@ void or_block_gradient(const or_problem *P, const double *r, int64_t i, double *
  * (eq. SemiRelaxedSubproblemImplement, Sec. 3.1): the minimising vertex is
  * a_i e_j with j the index of the smallest gradient entry.  Ties go to the
  * lowest index.  *margin receives (second smallest) - (smallest), the
- * distance to the nearest competing vertex (+inf when n == 1). */
-int64_t or_lmo(int64_t n, const double *grad, double *margin)
+ * distance to the nearest competing vertex (+inf when n == 1), and *runner
+ * the lowest index attaining the second smallest value (-1 when n == 1). */
+int64_t or_lmo2(int64_t n, const double *grad, double *margin, int64_t *runner)
 {
     int64_t best = 0;
     for (int64_t j = 1; j < n; ++j)
         if (grad[j] < grad[best]) best = j;
     double second = INFINITY;
+    int64_t second_j = -1;
     for (int64_t j = 0; j < n; ++j)
-        if (j != best && grad[j] < second) second = grad[j];
+        if (j != best && grad[j] < second) { second = grad[j]; second_j = j; }
     if (margin) *margin = second - grad[best];
+    if (runner) *runner = second_j;
     return best;
+}
+
+int64_t or_lmo(int64_t n, const double *grad, double *margin)
+{
+    return or_lmo2(n, grad, margin, NULL);
 }
 
 /* Decay step of Alg. 1 (Sec. 3.1), with m blocks and the global block-step
@@ -207,11 +215,16 @@ void or_init_plan(const or_problem *P, double *T)
  * input), form the block gradient, solve the LMO, choose the step (ELS or
  * decay), move t_i toward s_i, and carry the relaxed marginal along.
  * T (m x n) and r (= T^T 1 - b) are updated in place; *k is the global
- * block-step counter used by the decay rule.  Per-step traces may be NULL.
+ * block-step counter used by the decay rule.  Per-step traces may be NULL:
+ * the LMO vertex, the step, the margin to the runner-up vertex and the
+ * runner-up's index; tr_near (nsteps x 4) lists the columns whose gradient
+ * lies within near_tol of the minimum (lowest indices first, -1 padded), the
+ * set of vertices that are LMO answers up to rounding.
  * rule: 0 = exact line search, 1 = decay.  Returns 0, or -1 on a bad index. */
 int or_bcfw_steps(const or_problem *P, double *T, double *r, int64_t *k,
                   int rule, int64_t nsteps, const int32_t *idx,
-                  int32_t *tr_j, double *tr_gamma, double *tr_margin)
+                  int32_t *tr_j, double *tr_gamma, double *tr_margin,
+                  int32_t *tr_runner, int32_t *tr_near, double near_tol)
 {
     const int64_t m = P->m, n = P->n;
     double *grad = (double *)malloc(sizeof(double) * (size_t)n);
@@ -224,7 +237,8 @@ int or_bcfw_steps(const or_problem *P, double *T, double *r, int64_t *k,
         /* gradient of the selected block and its LMO vertex */
         or_block_gradient(P, r, i, grad);
         double margin;
-        int64_t js = or_lmo(n, grad, &margin);
+        int64_t runner;
+        int64_t js = or_lmo2(n, grad, &margin, &runner);
         for (int64_t j = 0; j < n; ++j) s[j] = 0.0;
         s[js] = P->a[i];
         /* step size */
@@ -237,6 +251,13 @@ int or_bcfw_steps(const or_problem *P, double *T, double *r, int64_t *k,
         if (tr_j) tr_j[st] = (int32_t)js;
         if (tr_gamma) tr_gamma[st] = gamma;
         if (tr_margin) tr_margin[st] = margin;
+        if (tr_runner) tr_runner[st] = (int32_t)runner;
+        if (tr_near) {
+            int cnt = 0;
+            for (int q = 0; q < 4; ++q) tr_near[st * 4 + q] = -1;
+            for (int64_t j = 0; j < n && cnt < 4; ++j)
+                if (grad[j] - grad[js] <= near_tol) tr_near[st * 4 + cnt++] = (int32_t)j;
+        }
         *k += 1;
     }
     free(grad); free(s); free(old);

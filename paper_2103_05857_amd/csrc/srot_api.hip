@@ -1,0 +1,330 @@
+// C ABI of libsrot (declared in include/srot.h): argument checking, workspace
+// layout, and the pass loop around the kernels in srot_kernels.hip.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/srot.h"
+#include "srot_internal.h"
+
+struct srot_handle {
+    srot::ProblemView P;
+    srot::DeviceState S;
+    srot_options opt;
+    hipStream_t stream;
+    int64_t k;  // global block-step counter (decay rule, sampler position)
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define SROT_HIP(call)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(SROT_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+    size_t T, r, idx, G, j, g, partials, scalars, flags, total;
+    int64_t idx_cap;
+    int32_t gap_blocks;
+};
+
+bool sizes_ok(int64_t m, int64_t n)
+{
+    return m >= 1 && n >= 1 && m <= 0x7fffffff && n <= 0x7fffffff;
+}
+
+Layout make_layout(int64_t m, int64_t n)
+{
+    Layout L;
+    // whole passes of indices, at least 65536 steps
+    int64_t passes = std::max<int64_t>(1, (65536 + m - 1) / m);
+    L.idx_cap = passes * m;
+    L.gap_blocks = srot::gap_blocks_for(m);
+    size_t off = 0;
+    L.T = off; off = align_up(off + sizeof(double) * (size_t)m * (size_t)n);
+    L.r = off; off = align_up(off + sizeof(double) * (size_t)n);
+    L.idx = off; off = align_up(off + sizeof(int32_t) * (size_t)L.idx_cap);
+    L.G = off; off = align_up(off + sizeof(double) * (size_t)m);
+    L.j = off; off = align_up(off + sizeof(int32_t) * (size_t)m);
+    L.g = off; off = align_up(off + sizeof(double) * (size_t)m);
+    L.partials = off; off = align_up(off + sizeof(double) * 4 * (size_t)L.gap_blocks);
+    L.scalars = off; off = align_up(off + sizeof(double) * 8);
+    L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
+    L.total = off;
+    return L;
+}
+
+bool options_ok(const srot_options *o)
+{
+    if (!o) return false;
+    if (!(o->w >= 0.0) || !isfinite(o->w)) return false;
+    if (o->step_rule != SROT_ELS && o->step_rule != SROT_DEC) return false;
+    if (o->sampling != SROT_UNIFORM && o->sampling != SROT_PERMUTE) return false;
+    if (!(o->eps >= 0.0)) return false;
+    if (o->max_passes < 0 || o->gap_every < 1) return false;
+    if (o->cost != SROT_COST_F32 && o->cost != SROT_COST_F64 && o->cost != SROT_COST_SQEUCLID)
+        return false;
+    return true;
+}
+
+// Draws `count` indices for steps k .. k+count-1 into the index buffer and
+// returns a pointer to the first; count is reduced to what fits.
+int draw_indices(srot_handle *h, int64_t k, int64_t *count, const int32_t **out)
+{
+    const int32_t m = h->P.m;
+    if (h->opt.sampling == SROT_UNIFORM) {
+        *count = std::min(*count, h->S.idx_cap);
+        SROT_HIP(srot::launch_sample_uniform(h->opt.seed, k, *count, m, h->S.idx, h->stream));
+        *out = h->S.idx;
+    } else {
+        const int64_t p0 = k / m, off = k - p0 * m;
+        const int64_t cap_passes = h->S.idx_cap / m;
+        const int64_t need = (off + *count + m - 1) / m;
+        const int64_t np = std::min(need, cap_passes);
+        *count = std::min(*count, np * m - off);
+        SROT_HIP(srot::launch_sample_permute(h->opt.seed, p0, np, m, h->S.idx, h->stream));
+        *out = h->S.idx + off;
+    }
+    return SROT_OK;
+}
+
+int run_steps(srot_handle *h, int64_t nsteps, int32_t *trace_j, double *trace_gamma)
+{
+    int64_t done = 0;
+    while (done < nsteps) {
+        int64_t cnt = nsteps - done;
+        const int32_t *idx = nullptr;
+        int rc = draw_indices(h, h->k, &cnt, &idx);
+        if (rc != SROT_OK) return rc;
+        SROT_HIP(srot::launch_chain(h->P, h->S, idx, h->k, cnt, h->opt.step_rule,
+                                    trace_j ? trace_j + done : nullptr,
+                                    trace_gamma ? trace_gamma + done : nullptr, h->stream));
+        h->k += cnt;
+        done += cnt;
+    }
+    return SROT_OK;
+}
+
+int measure_gap(srot_handle *h, double *out3)
+{
+    SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
+    double host[3];
+    SROT_HIP(hipMemcpyAsync(host, h->S.scalars, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+    SROT_HIP(hipStreamSynchronize(h->stream));
+    out3[0] = host[0]; out3[1] = host[1]; out3[2] = host[2];
+    return SROT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void srot_default_options(srot_options *opt)
+{
+    if (!opt) return;
+    opt->w = 1.0;
+    opt->step_rule = SROT_ELS;
+    opt->sampling = SROT_UNIFORM;
+    opt->seed = 0;
+    opt->eps = 1e-6;
+    opt->max_passes = 1000;
+    opt->gap_every = 1;
+    opt->cost = SROT_COST_F32;
+}
+
+size_t srot_workspace_size(int64_t m, int64_t n, const srot_options *opt)
+{
+    (void)opt;
+    if (!sizes_ok(m, n)) return 0;
+    return make_layout(m, n).total;
+}
+
+int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const float *X,
+              const float *Y, const double *a, const double *b, void *workspace, size_t ws_bytes,
+              const srot_options *opt, void *stream)
+{
+    if (!out) return fail(SROT_EINVAL, "srot_init: out is NULL");
+    *out = nullptr;
+    if (!sizes_ok(m, n)) return fail(SROT_EINVAL, "srot_init: need 1 <= m, n <= 2^31-1 (m=%lld n=%lld)",
+                                     (long long)m, (long long)n);
+    if (!options_ok(opt)) return fail(SROT_EINVAL, "srot_init: invalid options");
+    if (!a || !b) return fail(SROT_EINVAL, "srot_init: a and b are required");
+    if (opt->cost == SROT_COST_SQEUCLID) {
+        if (!X || !Y) return fail(SROT_EINVAL, "srot_init: X and Y are required for SROT_COST_SQEUCLID");
+    } else if (!C) {
+        return fail(SROT_EINVAL, "srot_init: C is required for a stored cost");
+    }
+    if (!workspace) return fail(SROT_EINVAL, "srot_init: workspace is NULL");
+    if (((uintptr_t)workspace) % kAlign != 0)
+        return fail(SROT_EINVAL, "srot_init: workspace must be 256-byte aligned");
+    const Layout L = make_layout(m, n);
+    if (ws_bytes < L.total)
+        return fail(SROT_ENOMEM, "srot_init: workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    srot_handle *h = (srot_handle *)calloc(1, sizeof(srot_handle));
+    if (!h) return fail(SROT_ENOMEM, "srot_init: out of host memory");
+    h->opt = *opt;
+    h->stream = (hipStream_t)stream;
+    h->k = 0;
+    h->P.m = (int32_t)m;
+    h->P.n = (int32_t)n;
+    h->P.cost = opt->cost;
+    h->P.C = (opt->cost == SROT_COST_SQEUCLID) ? nullptr : C;
+    h->P.X = X;
+    h->P.Y = Y;
+    h->P.a = a;
+    h->P.b = b;
+    h->P.w = opt->w;
+    char *base = (char *)workspace;
+    h->S.T = (double *)(base + L.T);
+    h->S.r = (double *)(base + L.r);
+    h->S.idx = (int32_t *)(base + L.idx);
+    h->S.idx_cap = L.idx_cap;
+    h->S.row_G = (double *)(base + L.G);
+    h->S.row_j = (int32_t *)(base + L.j);
+    h->S.row_g = (double *)(base + L.g);
+    h->S.partials = (double *)(base + L.partials);
+    h->S.gap_blocks = L.gap_blocks;
+    h->S.scalars = (double *)(base + L.scalars);
+    h->S.flags = (int32_t *)(base + L.flags);
+
+    int rc = SROT_OK;
+    int32_t flag = 0;
+    hipError_t e = hipMemsetAsync(h->S.flags, 0, sizeof(int32_t) * 8, h->stream);
+    if (e == hipSuccess) e = srot::launch_validate(h->P, h->S, h->stream);
+    if (e == hipSuccess) e = srot::launch_init_plan(h->P, h->S, h->stream);
+    if (e == hipSuccess) e = srot::launch_residual(h->P, h->S, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init: %s", hipGetErrorString(e));
+    else if (flag & 1) rc = fail(SROT_ENONFINITE, "srot_init: NaN/Inf in C, X, Y, a or b, or a negative weight");
+    if (rc != SROT_OK) {
+        free(h);
+        return rc;
+    }
+    *out = h;
+    return SROT_OK;
+}
+
+int srot_step(srot_handle *h, int64_t nsteps, const int32_t *idx, int32_t *trace_j,
+              double *trace_gamma)
+{
+    if (!h) return fail(SROT_EINVAL, "srot_step: NULL handle");
+    if (nsteps < 0) return fail(SROT_EINVAL, "srot_step: nsteps < 0");
+    if (nsteps == 0) return SROT_OK;
+    if (!idx) return run_steps(h, nsteps, trace_j, trace_gamma);
+    // caller-supplied indices: check them on the device before any update
+    int32_t flag = 0;
+    SROT_HIP(hipMemsetAsync(h->S.flags, 0, sizeof(int32_t), h->stream));
+    SROT_HIP(srot::launch_check_indices(idx, nsteps, h->P.m, h->S.flags, h->stream));
+    SROT_HIP(hipMemcpyAsync(&flag, h->S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    SROT_HIP(hipStreamSynchronize(h->stream));
+    if (flag & 2) return fail(SROT_EINVAL, "srot_step: block index outside [0, m)");
+    SROT_HIP(srot::launch_chain(h->P, h->S, idx, h->k, nsteps, h->opt.step_rule, trace_j,
+                                trace_gamma, h->stream));
+    h->k += nsteps;
+    return SROT_OK;
+}
+
+int srot_gap(srot_handle *h, double *out3, double *row_gap, int32_t *row_argmin)
+{
+    if (!h || !out3) return fail(SROT_EINVAL, "srot_gap: NULL argument");
+    int rc = measure_gap(h, out3);
+    if (rc != SROT_OK) return rc;
+    if (row_gap)
+        SROT_HIP(hipMemcpyAsync(row_gap, h->S.row_g, sizeof(double) * h->P.m, hipMemcpyDeviceToDevice, h->stream));
+    if (row_argmin)
+        SROT_HIP(hipMemcpyAsync(row_argmin, h->S.row_j, sizeof(int32_t) * h->P.m, hipMemcpyDeviceToDevice, h->stream));
+    if (row_gap || row_argmin) SROT_HIP(hipStreamSynchronize(h->stream));
+    return SROT_OK;
+}
+
+int srot_solve(srot_handle *h, double *out3, int64_t *passes)
+{
+    if (!h || !out3 || !passes) return fail(SROT_EINVAL, "srot_solve: NULL argument");
+    *passes = 0;
+    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
+    const int64_t m = h->P.m;
+    for (int64_t p = 0; p < h->opt.max_passes; ++p) {
+        int rc = run_steps(h, m, nullptr, nullptr);
+        if (rc != SROT_OK) return rc;
+        *passes = p + 1;
+        if ((p + 1) % h->opt.gap_every == 0 || p + 1 == h->opt.max_passes) {
+            rc = measure_gap(h, out3);
+            if (rc != SROT_OK) return rc;
+            if (out3[0] <= h->opt.eps) return SROT_OK;
+        }
+    }
+    return SROT_NOT_CONVERGED;
+}
+
+int srot_get_plan(srot_handle *h, double *T_out, double *r_out)
+{
+    if (!h) return fail(SROT_EINVAL, "srot_get_plan: NULL handle");
+    if (T_out)
+        SROT_HIP(hipMemcpyAsync(T_out, h->S.T, sizeof(double) * (size_t)h->P.m * (size_t)h->P.n,
+                                hipMemcpyDeviceToDevice, h->stream));
+    if (r_out)
+        SROT_HIP(hipMemcpyAsync(r_out, h->S.r, sizeof(double) * (size_t)h->P.n, hipMemcpyDeviceToDevice, h->stream));
+    return SROT_OK;
+}
+
+int srot_get_state(srot_handle *h, int64_t *k)
+{
+    if (!h || !k) return fail(SROT_EINVAL, "srot_get_state: NULL argument");
+    *k = h->k;
+    return SROT_OK;
+}
+
+int srot_set_state(srot_handle *h, const double *T_in, int64_t k)
+{
+    if (!h || !T_in || k < 0) return fail(SROT_EINVAL, "srot_set_state: bad argument");
+    SROT_HIP(hipMemcpyAsync(h->S.T, T_in, sizeof(double) * (size_t)h->P.m * (size_t)h->P.n,
+                            hipMemcpyDeviceToDevice, h->stream));
+    SROT_HIP(srot::launch_residual(h->P, h->S, h->stream));
+    h->k = k;
+    return SROT_OK;
+}
+
+void srot_destroy(srot_handle *h) { free(h); }
+
+const char *srot_strerror(int status)
+{
+    switch (status) {
+    case SROT_OK: return "ok";
+    case SROT_NOT_CONVERGED: return "not converged within max_passes";
+    case SROT_EINVAL: return "invalid argument";
+    case SROT_ENOMEM: return "workspace too small";
+    case SROT_ENONFINITE: return "non-finite or negative input";
+    case SROT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *srot_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""Python binding of libsrot (include/srot.h): argument marshalling only.
+
+Every function below has the name of the C entry point it calls and does no
+arithmetic of the method: tensors are passed by device pointer, the stream is
+torch's current stream, and the library's status codes become exceptions.
+The library must be built (`__graft_entry__.build()`); without it every call
+raises -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrot.so")
+
+SROT_OK = 0
+SROT_NOT_CONVERGED = 1
+SROT_EINVAL = -1
+SROT_ENOMEM = -2
+SROT_ENONFINITE = -3
+SROT_EHIP = -4
+
+SROT_ELS = 0
+SROT_DEC = 1
+SROT_UNIFORM = 0
+SROT_PERMUTE = 1
+SROT_COST_F32 = 0
+SROT_COST_F64 = 1
+SROT_COST_SQEUCLID = 2
+
+
+class SrotError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"srot status {status}: {msg}")
+        self.status = status
+
+
+class srot_options(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_double), ("step_rule", ctypes.c_int32),
+                ("sampling", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("eps", ctypes.c_double), ("max_passes", ctypes.c_int64),
+                ("gap_every", ctypes.c_int32), ("cost", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+def load():
+    """Loads libsrot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.srot_default_options.argtypes = [ctypes.POINTER(srot_options)]
+    L.srot_default_options.restype = None
+    L.srot_workspace_size.argtypes = [_i64, _i64, ctypes.POINTER(srot_options)]
+    L.srot_workspace_size.restype = ctypes.c_size_t
+    L.srot_init.argtypes = [ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                            ctypes.c_size_t, ctypes.POINTER(srot_options), _vp]
+    L.srot_init.restype = ctypes.c_int
+    L.srot_step.argtypes = [_vp, _i64, _vp, _vp, _vp]
+    L.srot_step.restype = ctypes.c_int
+    L.srot_gap.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _vp, _vp]
+    L.srot_gap.restype = ctypes.c_int
+    L.srot_solve.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    L.srot_solve.restype = ctypes.c_int
+    L.srot_get_plan.argtypes = [_vp, _vp, _vp]
+    L.srot_get_plan.restype = ctypes.c_int
+    L.srot_get_state.argtypes = [_vp, ctypes.POINTER(_i64)]
+    L.srot_get_state.restype = ctypes.c_int
+    L.srot_set_state.argtypes = [_vp, _vp, _i64]
+    L.srot_set_state.restype = ctypes.c_int
+    L.srot_destroy.argtypes = [_vp]
+    L.srot_destroy.restype = None
+    L.srot_strerror.argtypes = [ctypes.c_int]
+    L.srot_strerror.restype = ctypes.c_char_p
+    L.srot_last_error.argtypes = []
+    L.srot_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status, allow=(SROT_OK,)):
+    if status in allow:
+        return status
+    L = load()
+    raise SrotError(status, f"{L.srot_strerror(status).decode()}: {L.srot_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def srot_default_options(**kw):
+    opt = srot_options()
+    load().srot_default_options(ctypes.byref(opt))
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    return opt
+
+
+def srot_workspace_size(m, n, opt):
+    return int(load().srot_workspace_size(m, n, ctypes.byref(opt)))
+
+
+def srot_init(m, n, C, X, Y, a, b, workspace, opt):
+    h = ctypes.c_void_p()
+    _check(load().srot_init(ctypes.byref(h), m, n, _ptr(C), _ptr(X), _ptr(Y), _ptr(a), _ptr(b),
+                            _ptr(workspace), workspace.numel() * workspace.element_size(),
+                            ctypes.byref(opt), _stream()))
+    return h
+
+
+def srot_step(h, nsteps, idx=None, trace_j=None, trace_gamma=None):
+    _check(load().srot_step(h, nsteps, _ptr(idx), _ptr(trace_j), _ptr(trace_gamma)))
+
+
+def srot_gap(h, row_gap=None, row_argmin=None):
+    out = (ctypes.c_double * 3)()
+    _check(load().srot_gap(h, out, _ptr(row_gap), _ptr(row_argmin)))
+    return out[0], out[1], out[2]
+
+
+def srot_solve(h):
+    out = (ctypes.c_double * 3)()
+    passes = _i64()
+    st = _check(load().srot_solve(h, out, ctypes.byref(passes)), allow=(SROT_OK, SROT_NOT_CONVERGED))
+    return st, (out[0], out[1], out[2]), passes.value
+
+
+def srot_get_plan(h, T_out=None, r_out=None):
+    _check(load().srot_get_plan(h, _ptr(T_out), _ptr(r_out)))
+
+
+def srot_get_state(h):
+    k = _i64()
+    _check(load().srot_get_state(h, ctypes.byref(k)))
+    return k.value
+
+
+def srot_set_state(h, T_in, k):
+    _check(load().srot_set_state(h, _ptr(T_in), k))
+
+
+def srot_destroy(h):
+    if h:
+        load().srot_destroy(h)
+
+
+class Solver:
+    """Owns the device workspace of one handle and keeps its inputs alive.
+
+    C: (m, n) float32/float64 CUDA tensor, or None with X, Y (float32, N x 3)
+    for the fused squared-Euclidean cost.  a, b: float64 CUDA tensors."""
+
+    def __init__(self, a, b, C=None, X=None, Y=None, **options):
+        m, n = a.shape[0], b.shape[0]
+        if "cost" not in options:
+            if C is None:
+                options["cost"] = SROT_COST_SQEUCLID
+            else:
+                options["cost"] = SROT_COST_F64 if C.dtype == torch.float64 else SROT_COST_F32
+        self.opt = srot_default_options(**options)
+        self.m, self.n = m, n
+        self._keep = (a, b, C, X, Y)
+        nbytes = srot_workspace_size(m, n, self.opt)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=a.device)
+        self.h = srot_init(m, n, C, X, Y, a, b, self.workspace, self.opt)
+
+    def step(self, nsteps, idx=None, trace=False):
+        if trace:
+            tj = torch.empty(nsteps, dtype=torch.int32, device=self.workspace.device)
+            tg = torch.empty(nsteps, dtype=torch.float64, device=self.workspace.device)
+            srot_step(self.h, nsteps, idx, tj, tg)
+            return tj, tg
+        srot_step(self.h, nsteps, idx)
+        return None
+
+    def gap(self, per_row=False):
+        if per_row:
+            rg = torch.empty(self.m, dtype=torch.float64, device=self.workspace.device)
+            rj = torch.empty(self.m, dtype=torch.int32, device=self.workspace.device)
+            g, f, D = srot_gap(self.h, rg, rj)
+            return (g, f, D), rg, rj
+        return srot_gap(self.h)
+
+    def solve(self):
+        return srot_solve(self.h)
+
+    def plan(self):
+        T = torch.empty(self.m, self.n, dtype=torch.float64, device=self.workspace.device)
+        r = torch.empty(self.n, dtype=torch.float64, device=self.workspace.device)
+        srot_get_plan(self.h, T, r)
+        return T, r
+
+    @property
+    def k(self):
+        return srot_get_state(self.h)
+
+    def set_state(self, T, k):
+        srot_set_state(self.h, T, k)
+
+    def close(self):
+        if self.h:
+            srot_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
