@@ -145,12 +145,15 @@ int srot_solve(srot_handle *h, double *out3, int64_t *passes);
 int srot_get_plan(srot_handle *h, double *T_out, double *r_out);
 
 /* Checkpoint / resume: the state is (T, r, k).  srot_get_state writes the
- * block-step counter to *k (host).  srot_set_state loads a plan T (device,
- * m x n double, rows must lie on a_i * simplex up to rounding; not checked),
- * recomputes r from it and sets the counter to k.  With the counter-based
- * block-index stream a resumed run repeats the uninterrupted one. */
+ * block-step counter to *k (host); srot_get_plan copies T and r.
+ * srot_set_state loads a plan T (device, m x n double; rows must lie on
+ * a_i * simplex up to rounding, not checked), rebuilds the support masks, and
+ * either copies the residual r_in (device, n double) or, when r_in is NULL,
+ * recomputes it from T; the counter becomes k.  With r_in taken from the
+ * same run, a resumed run repeats the uninterrupted one bit for bit (the
+ * block-index stream is counter based). */
 int srot_get_state(srot_handle *h, int64_t *k);
-int srot_set_state(srot_handle *h, const double *T_in, int64_t k);
+int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64_t k);
 
 /* Destroys the handle (host memory only; the caller frees its buffers). */
 void srot_destroy(srot_handle *h);

@@ -47,10 +47,19 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t T, r, idx, G, j, g, partials, scalars, flags, total;
+    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, resume, Y4, total;
     int64_t idx_cap;
     int32_t gap_blocks;
 };
+
+// Mask words per row for any ownership the kernels may choose for n columns
+// (at most 512 threads with one word each, or the wide-row layout).
+size_t mask_words_per_row(int64_t n)
+{
+    const int64_t cpt_glb = (n + 511) / 512;
+    const int64_t words_glb = (cpt_glb + 31) / 32;
+    return (size_t)std::max<int64_t>(512, words_glb * 512);
+}
 
 bool sizes_ok(int64_t m, int64_t n)
 {
@@ -67,6 +76,7 @@ Layout make_layout(int64_t m, int64_t n)
     size_t off = 0;
     L.T = off; off = align_up(off + sizeof(double) * (size_t)m * (size_t)n);
     L.r = off; off = align_up(off + sizeof(double) * (size_t)n);
+    L.mask = off; off = align_up(off + sizeof(uint32_t) * (size_t)m * mask_words_per_row(n));
     L.idx = off; off = align_up(off + sizeof(int32_t) * (size_t)L.idx_cap);
     L.G = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.j = off; off = align_up(off + sizeof(int32_t) * (size_t)m);
@@ -74,6 +84,8 @@ Layout make_layout(int64_t m, int64_t n)
     L.partials = off; off = align_up(off + sizeof(double) * 4 * (size_t)L.gap_blocks);
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
+    L.resume = off; off = align_up(off + sizeof(int64_t));
+    L.Y4 = off; off = align_up(off + 16 * (size_t)n);
     L.total = off;
     return L;
 }
@@ -200,8 +212,11 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->P.b = b;
     h->P.w = opt->w;
     char *base = (char *)workspace;
+    h->P.Y4 = Y ? (const float4 *)(base + L.Y4) : nullptr;
     h->S.T = (double *)(base + L.T);
     h->S.r = (double *)(base + L.r);
+    h->S.mask = (uint32_t *)(base + L.mask);
+    h->S.own = srot::choose_ownership(n, opt->cost, ((uintptr_t)C % 16u) == 0u);
     h->S.idx = (int32_t *)(base + L.idx);
     h->S.idx_cap = L.idx_cap;
     h->S.row_G = (double *)(base + L.G);
@@ -211,13 +226,16 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->S.gap_blocks = L.gap_blocks;
     h->S.scalars = (double *)(base + L.scalars);
     h->S.flags = (int32_t *)(base + L.flags);
+    h->S.resume = (int64_t *)(base + L.resume);
 
     int rc = SROT_OK;
     int32_t flag = 0;
     hipError_t e = hipMemsetAsync(h->S.flags, 0, sizeof(int32_t) * 8, h->stream);
     if (e == hipSuccess) e = srot::launch_validate(h->P, h->S, h->stream);
+    if (e == hipSuccess) e = srot::launch_pad_points(h->P, h->stream);
     if (e == hipSuccess) e = srot::launch_init_plan(h->P, h->S, h->stream);
     if (e == hipSuccess) e = srot::launch_residual(h->P, h->S, h->stream);
+    if (e == hipSuccess) e = srot::launch_mask_build(h->P, h->S, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init: %s", hipGetErrorString(e));
@@ -300,12 +318,17 @@ int srot_get_state(srot_handle *h, int64_t *k)
     return SROT_OK;
 }
 
-int srot_set_state(srot_handle *h, const double *T_in, int64_t k)
+int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64_t k)
 {
     if (!h || !T_in || k < 0) return fail(SROT_EINVAL, "srot_set_state: bad argument");
     SROT_HIP(hipMemcpyAsync(h->S.T, T_in, sizeof(double) * (size_t)h->P.m * (size_t)h->P.n,
                             hipMemcpyDeviceToDevice, h->stream));
-    SROT_HIP(srot::launch_residual(h->P, h->S, h->stream));
+    if (r_in)
+        SROT_HIP(hipMemcpyAsync(h->S.r, r_in, sizeof(double) * (size_t)h->P.n,
+                                hipMemcpyDeviceToDevice, h->stream));
+    else
+        SROT_HIP(srot::launch_residual(h->P, h->S, h->stream));
+    SROT_HIP(srot::launch_mask_build(h->P, h->S, h->stream));
     h->k = k;
     return SROT_OK;
 }

@@ -14,15 +14,33 @@ struct ProblemView {
     const void *C;         // m x n (float or double), or nullptr
     const float *X;        // m x 3
     const float *Y;        // n x 3
+    const float4 *Y4;      // n, Y padded to 16 bytes (workspace), or nullptr
     const double *a;       // m
     const double *b;       // n
     double w;
+};
+
+// Column ownership shared by the step and gap kernels of one handle: thread
+// `tid` of an nt-thread workgroup owns columns
+//   j(u) = ((u / vec) * nt + tid) * vec + u % vec,   u < cpt,
+// i.e. groups of vec adjacent columns strided by nt groups.  The support of
+// row i is kept as bitmasks: bit (u % 32) of word
+//   mask[(i * words + u / 32) * nt + tid]
+// is set iff T[i][j(u)] != 0, so kernels touch only nonzero entries.
+struct Ownership {
+    int32_t nt;     // threads per workgroup
+    int32_t cpt;    // columns per thread
+    int32_t vec;    // adjacent columns per group (1, 2 or 4)
+    int32_t words;  // ceil(cpt / 32)
+    int32_t reg;    // 1: register-resident residual variant (cpt <= 32)
 };
 
 // Device state carved out of the caller's workspace.
 struct DeviceState {
     double *T;             // m x n dense plan
     double *r;             // n, residual T^T 1 - b
+    uint32_t *mask;        // m x words x nt support bitmasks
+    Ownership own;
     int32_t *idx;          // index buffer (idx_cap entries)
     int64_t idx_cap;
     double *row_G;         // m, min_j of the block gradient (gap sweep)
@@ -32,7 +50,13 @@ struct DeviceState {
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
     int32_t *flags;        // 8: [0] validation/index error flag
+    int64_t *resume;       // step at which the prefetching chain kernel stopped
 };
+
+// Ownership chosen for an n-column problem with the given cost storage;
+// aligned16: the cost matrix base is 16-byte aligned (honours
+// SROT_CHAIN_VARIANT).
+Ownership choose_ownership(int64_t n, int cost, bool aligned16);
 
 // Launch wrappers (srot_kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
@@ -41,6 +65,8 @@ hipError_t launch_check_indices(const int32_t *idx, int64_t count, int32_t m, in
                                 hipStream_t stream);
 hipError_t launch_init_plan(const ProblemView &P, const DeviceState &S, hipStream_t stream);
 hipError_t launch_residual(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+hipError_t launch_mask_build(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+hipError_t launch_pad_points(const ProblemView &P, hipStream_t stream);
 hipError_t launch_sample_uniform(uint64_t seed, int64_t k0, int64_t count, int32_t m,
                                  int32_t *out, hipStream_t stream);
 hipError_t launch_sample_permute(uint64_t seed, int64_t p0, int64_t npasses, int32_t m,

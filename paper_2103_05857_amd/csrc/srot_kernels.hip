@@ -5,19 +5,24 @@
 // marginal is the column sum with residual r = T^T 1 - b, and w is the
 // penalty weight (the paper's 1/lambda).
 //
+// Column ownership: thread tid of an NT-thread workgroup owns columns
+// j = u * NT + tid.  Loads of a cost row are then coalesced, the residual
+// entries r_j a thread owns never move, and every update of t_ij and r_j is
+// done by its owner: no atomics, no cross-thread hazards on T or r.  The
+// support of each row is a bitmask per (row, thread) (see Ownership), so a
+// step reads the cost row plus only the nonzero plan entries (a BCFW row
+// without away steps holds a handful of atoms).
+//
 // Kernels
-//   chain_reg_kernel  one workgroup runs a sequence of BCFW block steps
-//                     (Alg. 1).  Thread `tid` owns columns j = q*NT + tid, so
-//                     r_j lives in that thread's registers for the whole launch
-//                     and every per-column update is thread-local; only the
-//                     LMO argmin and the line-search sums cross threads (one
-//                     wave64 butterfly + one LDS exchange, one barrier/step).
-//                     The next row of C and T is prefetched during the
-//                     current step (the row sequence is known in advance).
-//   chain_glb_kernel  same step for n too large for registers: r stays in
-//                     global memory (L2) with the same fixed column ownership.
-//   gap_kernel        per-pass duality-gap sweep (Thm 2): one wave per row,
-//                     streams the row of C and T once, HBM bound.
+//   chain_kernel      one workgroup runs a sequence of BCFW block steps
+//                     (Alg. 1) with r in registers (n <= NT * 32).  The next
+//                     four rows (cost row, mask, a_i) and the next two rows'
+//                     plan entries are prefetched: the row sequence is known
+//                     in advance.  A step is two workgroup reductions: the
+//                     LMO argmin, then the line-search sums over the support.
+//   chain_glb_kernel  same step for wider rows: r in global memory (L2).
+//   gap_kernel        per-pass duality-gap sweep (Thm 2), one workgroup per
+//                     row at a time, streaming the cost row once: HBM bound.
 //   gap_final_kernel  deterministic fixed-order reduction of the sweep.
 //   sample kernels    counter-based Philox4x64-10 block indices.
 #include <hip/hip_runtime.h>
@@ -32,114 +37,6 @@
 
 namespace srot {
 
-// ---------------------------------------------------------------------------
-// LMO + line-search partial over a set of columns of one block.
-//
-// For the block gradient v_j = c_ij + w r_j of row i and its plan entries t_j:
-//   v, j   smallest v and its lowest index (the LMO vertex,
-//          eq. SemiRelaxedSubproblemImplement, ties to the lowest index)
-//   t      t_j at that index
-//   Q      sum of t_j^2 over the other columns of the set
-//   P      sum of t_j (v_j - v)   (>= 0 term by term)
-//   Ts     sum of t_j
-// With s_i = a_i e_j*, the exact line search (eq. SemiRelaxedBCFWStep) needs
-//   <t_i - s_i, grad_i f> = P + (Ts - a_i) v  ~  P   (row sums equal a_i)
-//   ||t_i - s_i||^2       = Q + (t - a_i)^2
-// Both are accumulated without cancellation: when the running minimum moves
-// down, earlier terms grow by (old v - new v) * Ts, and the displaced
-// winner's t^2 joins Q.
-// ---------------------------------------------------------------------------
-struct ArgPart {
-    double v, t, Q, P, Ts;
-    int j;
-};
-
-__device__ __forceinline__ void part_init(ArgPart &p)
-{
-    p.v = INFINITY; p.t = 0.0; p.Q = 0.0; p.P = 0.0; p.Ts = 0.0; p.j = 0x7fffffff;
-}
-
-// Columns must be pushed in increasing j within one partial.
-__device__ __forceinline__ void part_push(ArgPart &p, double v, double t, int j)
-{
-    if (v < p.v) {
-        if (p.Ts != 0.0) p.P += (p.v - v) * p.Ts;
-        p.Q += p.t * p.t;
-        p.v = v; p.t = t; p.j = j;
-    } else {
-        p.Q += t * t;
-        p.P += t * (v - p.v);
-    }
-    p.Ts += t;
-}
-
-// Symmetric in (A, B) bit for bit: every sum is formed from commutative pairs.
-__device__ __forceinline__ ArgPart part_merge(const ArgPart &A, const ArgPart &B)
-{
-    const bool bw = (B.v < A.v) || (B.v == A.v && B.j < A.j);
-    const ArgPart &W = bw ? B : A;
-    const ArgPart &L = bw ? A : B;
-    ArgPart o;
-    o.v = W.v; o.t = W.t; o.j = W.j;
-    o.Q = (A.Q + B.Q) + L.t * L.t;
-    const double pa = (A.Ts != 0.0) ? (A.v - W.v) * A.Ts : 0.0;
-    const double pb = (B.Ts != 0.0) ? (B.v - W.v) * B.Ts : 0.0;
-    o.P = (A.P + B.P) + (pa + pb);
-    o.Ts = A.Ts + B.Ts;
-    return o;
-}
-
-__device__ __forceinline__ ArgPart part_shfl_xor(const ArgPart &p, int off)
-{
-    ArgPart o;
-    o.v = __shfl_xor(p.v, off);
-    o.t = __shfl_xor(p.t, off);
-    o.Q = __shfl_xor(p.Q, off);
-    o.P = __shfl_xor(p.P, off);
-    o.Ts = __shfl_xor(p.Ts, off);
-    o.j = __shfl_xor(p.j, off);
-    return o;
-}
-
-__device__ __forceinline__ ArgPart wave_reduce(ArgPart p)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) p = part_merge(p, part_shfl_xor(p, off));
-    return p;
-}
-
-// Block-wide reduction; every thread returns the same result (waves merged in
-// a fixed order).  `sh` must not be reused until one more barrier has passed
-// (callers alternate two slots).
-template <int NW>
-__device__ __forceinline__ ArgPart block_reduce(ArgPart p, ArgPart *sh)
-{
-    p = wave_reduce(p);
-    if (NW == 1) return p;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sh[wid] = p;
-    __syncthreads();
-    ArgPart res = sh[0];
-#pragma unroll
-    for (int k = 1; k < NW; ++k) res = part_merge(res, sh[k]);
-    return res;
-}
-
-// Step size of Alg. 1: decay 2m/(k+2m), or the exact line search
-// (eq. SemiRelaxedBCFWStep) restricted to [0, 1]; with a vanishing
-// denominator the objective is linear along the segment.
-__device__ __forceinline__ double step_size(int rule, int64_t k, int32_t m, double w,
-                                            const ArgPart &res, double ai)
-{
-    if (rule == SROT_DEC) return (2.0 * (double)m) / ((double)k + 2.0 * (double)m);
-    const double num = res.P;
-    const double dt = res.t - ai;
-    const double den = w * (res.Q + dt * dt);
-    if (!(num > 0.0)) return 0.0;
-    if (den == 0.0 || num >= den) return 1.0;
-    return num / den;
-}
-
 __device__ __forceinline__ double sqdist(float x0, float x1, float x2, float y0, float y1, float y2)
 {
     const double d0 = (double)x0 - (double)y0;
@@ -149,286 +46,947 @@ __device__ __forceinline__ double sqdist(float x0, float x1, float x2, float y0,
 }
 
 // ---------------------------------------------------------------------------
-// Block-step chain, r in registers.  Requires n <= NT * CPT.
+// Wave and workgroup reductions.
+//
+// Inside a wave: four DPP exchanges (quad xor 1, quad xor 2, half-row mirror,
+// row mirror) give every lane of a 16-lane row the row's result, then the
+// four row results are read with v_readlane and combined in row order.  No
+// LDS traffic, so these never wait behind outstanding LDS or scalar loads.
+// Across waves: one LDS slot per wave, one barrier, partials combined in wave
+// order.  Every thread ends with the same bits.  Callers pass a two-slot LDS
+// buffer indexed by step parity, so a slot is rewritten only after a later
+// barrier.  All lanes of the workgroup must be active.
 // ---------------------------------------------------------------------------
-template <int NT, int CPT, int COST>
-__global__ __launch_bounds__(NT) void chain_reg_kernel(ProblemView P, double *__restrict__ T,
-                                                       double *__restrict__ rg,
-                                                       const int32_t *__restrict__ idx, int64_t k0,
-                                                       int64_t nsteps, int rule,
-                                                       int32_t *__restrict__ trace_j,
-                                                       double *__restrict__ trace_gamma)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const int lo = dpp_i32<CTRL>((int)(unsigned)u);
+    const int hi = dpp_i32<CTRL>((int)(unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
+
+// LMO: smallest gradient value, ties to the lowest column index
+// (eq. SemiRelaxedSubproblemImplement).
+__device__ __forceinline__ void argmin_merge(double &v, int &j, double ov, int oj)
+{
+    const bool take = (ov < v) || (ov == v && oj < j);
+    v = take ? ov : v;
+    j = take ? oj : j;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmin_dpp(double &v, int &j)
+{
+    argmin_merge(v, j, dpp_f64<CTRL>(v), dpp_i32<CTRL>(j));
+}
+
+__device__ __forceinline__ void wave_argmin(double &v, int &j)
+{
+    argmin_dpp<DPP_QUAD_XOR1>(v, j);
+    argmin_dpp<DPP_QUAD_XOR2>(v, j);
+    argmin_dpp<DPP_HALF_MIRROR>(v, j);
+    argmin_dpp<DPP_MIRROR>(v, j);
+    double rv = readlane_f64(v, 0);
+    int rj = __builtin_amdgcn_readlane(j, 0);
+#pragma unroll
+    for (int row = 1; row < 4; ++row)
+        argmin_merge(rv, rj, readlane_f64(v, 16 * row), __builtin_amdgcn_readlane(j, 16 * row));
+    v = rv;
+    j = rj;
+}
+
+template <int NW>
+__device__ __forceinline__ void block_argmin(double &v, int &j, double *sv, int *sj)
+{
+    wave_argmin(v, j);
+    if (NW == 1) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sv[wid] = v; sj[wid] = j; }
+    __syncthreads();
+    v = sv[0]; j = sj[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) argmin_merge(v, j, sv[k], sj[k]);
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sum(double (&x)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += dpp_f64<DPP_QUAD_XOR1>(x[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += dpp_f64<DPP_QUAD_XOR2>(x[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += dpp_f64<DPP_HALF_MIRROR>(x[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += dpp_f64<DPP_MIRROR>(x[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = readlane_f64(x[k], 0);
+        s += readlane_f64(x[k], 16);
+        s += readlane_f64(x[k], 32);
+        s += readlane_f64(x[k], 48);
+        x[k] = s;
+    }
+}
+
+// Sum of K doubles.  Waves in which every lane holds zeros skip the exchange
+// (their partial is exactly zero either way).
+template <int NW, int K>
+__device__ __forceinline__ void block_sum(double (&x)[K], double (*sh)[K])
+{
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) any |= (x[k] != 0.0);
+    if (__any(any)) wave_sum<K>(x);
+    if (NW == 1) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[wid][k] = x[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = sh[0][k];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) s += sh[q][k];
+        x[k] = s;
+    }
+}
+
+// Waits for every outstanding vector-memory operation of the wave.  Ending a
+// rarely taken branch that touches memory this way lets the compiler keep
+// exact wait counts for the prefetched data on the common path.
+__device__ __forceinline__ void drain_memory()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15) on gfx9
+}
+
+// Copies a wave-uniform value into a vector register, so that loads addressed
+// by it are vector loads (counted by vmcnt).  Scalar loads share their wait
+// counter with LDS traffic, and a scalar miss on a random row's metadata
+// would stall every reduction behind it.
+__device__ __forceinline__ int in_vgpr(int x)
+{
+    int y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+
+// Step size of Alg. 1: decay 2m/(k+2m), or the exact line search
+// (eq. SemiRelaxedBCFWStep) restricted to [0, 1].  With s_i = a_i e_j*:
+//   num = <t_i - s_i, grad_i f> = sum_j t_j (v_j - G)   (row sums = a_i)
+//   den = w ||t_i - s_i||^2     = w (sum_{j != j*} t_j^2 + (t_j* - a_i)^2)
+// both free of cancellation; with a vanishing denominator the objective is
+// linear along the segment.
+__device__ __forceinline__ double step_size(int rule, int64_t k, int32_t m, double w, double num,
+                                            double q_off, double tstar, double ai)
+{
+    if (rule == SROT_DEC) return (2.0 * (double)m) / ((double)k + 2.0 * (double)m);
+    const double dt = tstar - ai;
+    const double den = w * (q_off + dt * dt);
+    if (!(num > 0.0)) return 0.0;
+    if (den == 0.0 || num >= den) return 1.0;
+    return num / den;
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access.  A row of T (or a mask row) is addressed through a
+// buffer resource whose range is that row; an offset of 0x80000000 lies
+// outside every range, so a load there returns 0 and a store there is
+// dropped without touching memory.  This lets each step issue a fixed,
+// branch-free sequence of loads and stores (predication by offset), which
+// keeps the compiler's count of outstanding memory operations exact: the
+// prefetched rows are then waited on individually instead of by a full
+// drain of the memory queue.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kOOB = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9-family raw buffer
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kRawBufferWord3);
+}
+__device__ __forceinline__ double buf_load_f64(__amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_store_f64(double v, __amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store_u32(unsigned v, __amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, (int)off, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Column ownership (also used by the gap sweep and the mask builder): thread
+// tid owns the columns j = ((u / VEC) * NT + tid) * VEC + u % VEC, u < CPT:
+// groups of VEC adjacent columns, strided by NT groups.  A wave then reads a
+// cost row with fully coalesced 16-byte loads, and bit u of the thread's mask
+// word marks column j in the support of the row.
+// ---------------------------------------------------------------------------
+template <int NT, int VEC>
+__device__ __forceinline__ int owned_col(int u, int tid)
+{
+    return ((u / VEC) * NT + tid) * VEC + (u % VEC);
+}
+
+// Loads this thread's CPT entries of a cost row (clamped to valid memory;
+// entries beyond column n - 1 are garbage and must be masked by the caller).
+template <int NT, int CPT, int VEC, typename CT>
+__device__ __forceinline__ void load_cost_row(const CT *__restrict__ row, int n, int tid, CT (&c)[CPT])
+{
+    if constexpr (VEC == 1) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = u * NT + tid;
+            c[u] = row[j < n ? j : n - 1];
+        }
+    } else {
+        // 16-byte vectors: VEC = 16 / sizeof(CT); n % VEC == 0, rows 16-byte aligned
+        constexpr int G = CPT / VEC;
+        const int ng = n / VEC;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int gi = g * NT + tid;
+            const int gc = gi < ng ? gi : ng - 1;
+            if constexpr (sizeof(CT) == 4) {
+                const float4 v = reinterpret_cast<const float4 *>(row)[gc];
+                c[g * 4 + 0] = v.x; c[g * 4 + 1] = v.y; c[g * 4 + 2] = v.z; c[g * 4 + 3] = v.w;
+            } else {
+                const double2 v = reinterpret_cast<const double2 *>(row)[gc];
+                c[g * 2 + 0] = v.x; c[g * 2 + 1] = v.y;
+            }
+        }
+    }
+}
+
+// (1 - gamma) t + gamma * add: the block update of Alg. 1 for one entry, one
+// expression shared by every code path so that all paths round alike.
+__device__ __forceinline__ double blend(double t, double gamma, double add)
+{
+    return (1.0 - gamma) * t + add;
+}
+
+// ---------------------------------------------------------------------------
+// Block-step chain for rows of at most NT * CPT columns (CPT <= 32; VEC > 1
+// needs n % VEC == 0 and 16-byte aligned cost rows), in two kernels.
+//
+// chain_kernel keeps the per-column work of a step to the gradient entry and
+// the LMO argmin; everything else touches only the support of the row:
+//   * r lives in LDS in ownership-major order (entry (u, tid) for column
+//     j(u)); only its owner thread reads or writes an entry, so no barrier
+//     guards it, and the few support entries can be indexed dynamically.
+//   * the support ("atoms") of row i in a thread's columns: the entries at
+//     the (at most) KA lowest bits of its mask word, requested two steps
+//     ahead together with their cost entries.
+//   * per step one workgroup exchange: each wave reduces its argmin and,
+//     relative to its own minimum, its line-search partial sums; the waves'
+//     partials are merged in wave order with cancellation-free formulas.
+// Every memory operation in the steady-state loop is unconditional (absent
+// slots point out of range), which keeps the compiler's count of outstanding
+// vector-memory operations exact, so the prefetched rows (DA ahead) and
+// atoms (2 ahead) are waited on individually.  A row updated after its data
+// was requested is patched from registers.  If a thread's row holds more
+// than KA atoms (rare), or once the last full group of DA steps is done, the
+// kernel stops and records the step to resume from.
+//
+// chain_tail_kernel finishes the remaining steps one at a time with plain
+// loads of every support entry (no prefetch, any support size).
+// ---------------------------------------------------------------------------
+template <int CPT, typename CT>
+struct RowSlot {
+    int i;
+    double a;
+    uint32_t mk;
+    CT c[CPT];
+    float x[3];
+};
+
+constexpr int KA = 4;  // atoms per (row, thread) handled by the prefetching kernel
+
+template <typename CT>
+struct AtomSlot {
+    double t[KA];  // plan entries at the KA lowest mask bits (0 where absent)
+    CT c[KA];      // their cost entries (stored cost)
+    float y[KA][3];  // their target points (fused cost)
+    int q[KA];     // local column indices, -1 where absent
+    uint32_t mk;   // the mask the atoms were read with
+};
+
+// Local column indices of the KA lowest set bits of mk (-1 where absent).
+__device__ __forceinline__ void low_bits(uint32_t mk, int (&q)[KA])
+{
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        q[k] = mk ? __ffs(mk) - 1 : -1;
+        mk &= mk - 1u;
+    }
+}
+
+// One wave's share of a step: its LMO candidate (v, j) -- the smallest
+// gradient entry of its columns, lowest index on ties -- with, over the
+// support entries t of its columns,
+//   P = sum t (v_col - v),  Q = sum of t^2 off column j,  tj = t at j,
+//   Ts = sum t,  and a flag (some thread has more atoms than the kernel reads).
+struct WavePart {
+    double v, P, Q, tj, Ts;
+    int j, more;
+};
+
+// Cancellation-free merge: moving the minimum down from v_A to v adds
+// (v_A - v) * Ts_A to P_A; the loser's entry at its own argmin joins Q.
+__device__ __forceinline__ WavePart wave_part_merge(const WavePart &A, const WavePart &B)
+{
+    const bool bw = (B.v < A.v) || (B.v == A.v && B.j < A.j);
+    const WavePart &W = bw ? B : A;
+    const WavePart &L = bw ? A : B;
+    WavePart o;
+    o.v = W.v; o.j = W.j; o.tj = W.tj;
+    o.Q = (A.Q + B.Q) + L.tj * L.tj;
+    const double pa = (A.Ts != 0.0) ? (A.v - W.v) * A.Ts : 0.0;
+    const double pb = (B.Ts != 0.0) ? (B.v - W.v) * B.Ts : 0.0;
+    o.P = (A.P + B.P) + (pa + pb);
+    o.Ts = A.Ts + B.Ts;
+    o.more = A.more | B.more;
+    return o;
+}
+
+// Wave minimum of v (DPP within rows of 16, then the four row results).
+__device__ __forceinline__ double wave_min(double v)
+{
+    v = fmin(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmin(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmin(v, dpp_f64<DPP_HALF_MIRROR>(v));
+    v = fmin(v, dpp_f64<DPP_MIRROR>(v));
+    double m = readlane_f64(v, 0);
+    m = fmin(m, readlane_f64(v, 16));
+    m = fmin(m, readlane_f64(v, 32));
+    m = fmin(m, readlane_f64(v, 48));
+    return m;
+}
+
+// Sum of x over the lanes set in `lanes`, in lane order (wave-uniform result).
+__device__ __forceinline__ double lanes_sum(double x, unsigned long long lanes)
+{
+    double s = 0.0;
+    while (lanes) {
+        const int l = __ffsll((long long)lanes) - 1;
+        lanes &= lanes - 1ull;
+        s += readlane_f64(x, l);
+    }
+    return s;
+}
+
+template <int NT, int CPT, int VEC, int COST, bool TRACE>
+__global__ __launch_bounds__(NT) void chain_kernel(ProblemView P, double *__restrict__ T,
+                                                   double *__restrict__ rg,
+                                                   uint32_t *__restrict__ M,
+                                                   const int32_t *__restrict__ idx, int64_t k0,
+                                                   int64_t nsteps, int rule,
+                                                   int32_t *__restrict__ trace_j,
+                                                   double *__restrict__ trace_gamma,
+                                                   int64_t *__restrict__ resume)
+{
+    static_assert(CPT <= 32 && CPT % VEC == 0 && CPT % 2 == 0, "one mask word per thread");
+    using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
+    constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
+    constexpr int NW = NT / 64;
+    constexpr int DA = 4;  // rows requested ahead (cost row, mask, a_i)
+    __shared__ double r_lds[CPT * NT];      // r, entry (u, tid) at ((u/2)*NT + tid)*2 + u%2
+    __shared__ WavePart s_part[2][NW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = P.n, m = P.m;
+    const double w = P.w;
+    const CT *__restrict__ C = (const CT *)P.C;
+    const float4 *__restrict__ Y4 = P.Y4;
+    const unsigned row_bytes = (unsigned)n * 8u;
+    const int64_t nfull = nsteps - nsteps % DA;
+    auto r_at = [&](int u) -> int { return ((u >> 1) * NT + tid) * 2 + (u & 1); };
+
+    bool full = true;  // every column this thread owns is a real column
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int j = owned_col<NT, VEC>(u, tid);
+        r_lds[r_at(u)] = (j < n) ? rg[j] : 0.0;
+        full &= (j < n);
+    }
+    float y0[CPT], y1[CPT], y2[CPT];
+    if constexpr (FUSED) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            const float4 yv = Y4[j < n ? j : n - 1];
+            y0[u] = yv.x; y1[u] = yv.y; y2[u] = yv.z;
+        }
+    }
+
+    RowSlot<CPT, CT> ring[DA];
+    AtomSlot<CT> at[2];
+
+    // row i's a_i, this thread's mask word and cost entries (vector loads:
+    // i is held in a vector register)
+    auto issue_row = [&](RowSlot<CPT, CT> &S, int i) {
+        S.i = i;
+        S.a = P.a[i];
+        S.mk = M[(size_t)i * NT + tid];
+        if constexpr (FUSED) {
+            S.x[0] = P.X[3 * i + 0]; S.x[1] = P.X[3 * i + 1]; S.x[2] = P.X[3 * i + 2];
+        } else {
+            load_cost_row<NT, CPT, VEC, CT>(C + (size_t)i * (size_t)n, n, tid, S.c);
+        }
+    };
+    // plan and cost entries at the KA lowest bits of mk in row i
+    auto issue_atoms = [&](AtomSlot<CT> &A, int i, uint32_t mk) {
+        const __amdgpu_buffer_rsrc_t rt = buf_rsrc(T + (size_t)i * (size_t)n, row_bytes);
+        A.mk = mk;
+        low_bits(mk, A.q);
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            const unsigned col = A.q[k] >= 0 ? (unsigned)owned_col<NT, VEC>(A.q[k], tid) : 0u;
+            A.t[k] = buf_load_f64(rt, A.q[k] >= 0 ? col * 8u : kOOB);
+            if constexpr (FUSED) {
+                const float4 yv = Y4[col];
+                A.y[k][0] = yv.x;
+                A.y[k][1] = yv.y;
+                A.y[k][2] = yv.z;
+            } else {
+                const __amdgpu_buffer_rsrc_t rc = buf_rsrc(C + (size_t)i * (size_t)n, (unsigned)(n * sizeof(CT)));
+                if constexpr (sizeof(CT) == 4)
+                    A.c[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(col * 4u), 0, 0));
+                else
+                    A.c[k] = buf_load_f64(rc, col * 8u);
+            }
+        }
+    };
+
+    // block indices are read 2*DA steps ahead, through vector loads
+    const int32_t *__restrict__ idxv = idx + in_vgpr(0);
+    const int64_t last = nsteps - 1;
+    int nidx[DA];
+#pragma unroll
+    for (int u = 0; u < DA; ++u) {
+        issue_row(ring[u], idxv[u < last ? u : last]);
+        nidx[u] = idxv[DA + u < last ? DA + u : last];
+    }
+    issue_atoms(at[0], __builtin_amdgcn_readfirstlane(ring[0].i), ring[0].mk);
+    issue_atoms(at[1], __builtin_amdgcn_readfirstlane(ring[1].i), ring[1].mk);
+
+    // the two most recent updates (rows and new masks); F holds the atoms of
+    // the latest one when the next step visits the same row
+    int f1i = -1, f2i = -1;
+    uint32_t f1m = 0u, f2m = 0u;
+    AtomSlot<CT> F;
+
+    int64_t done = nfull;
+    for (int64_t s0 = 0; s0 < nfull; s0 += DA) {
+        bool stop = false;
+#pragma unroll
+        for (int slot = 0; slot < DA; ++slot) {
+            const int64_t s = s0 + slot;
+            RowSlot<CPT, CT> &S = ring[slot];
+            AtomSlot<CT> &A = (S.i == f1i) ? F : at[slot & 1];
+            const int i = __builtin_amdgcn_readfirstlane(S.i);
+            const double ai = S.a;
+            const size_t base = (size_t)i * (size_t)n;
+            const uint32_t mk = A.mk;
+            const int more = __popc(mk) > KA;
+
+            // gradient entries c_ij + w r_j (eq. RelaxedGradient) and the
+            // thread's smallest one, lowest column on ties
+            double vv[CPT];
+            double best = INFINITY;
+#pragma unroll
+            for (int u = 0; u < CPT; u += 2) {
+                const double2 rr = *reinterpret_cast<const double2 *>(&r_lds[r_at(u)]);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    double c;
+                    if constexpr (FUSED) c = sqdist(S.x[0], S.x[1], S.x[2], y0[u + e], y1[u + e], y2[u + e]);
+                    else c = (double)S.c[u + e];
+                    vv[u + e] = c + w * (e ? rr.y : rr.x);
+                }
+            }
+            if (!full) {
+#pragma unroll
+                for (int u = 0; u < CPT; ++u)
+                    vv[u] = (owned_col<NT, VEC>(u, tid) < n) ? vv[u] : INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) best = fmin(best, vv[u]);
+            int bj = 0x7fffffff;
+#pragma unroll
+            for (int u = CPT - 1; u >= 0; --u) bj = (vv[u] == best) ? owned_col<NT, VEC>(u, tid) : bj;
+
+            // the wave's LMO candidate (eq. SemiRelaxedSubproblemImplement)
+            WavePart wp;
+            wp.v = wave_min(best);
+            {
+                unsigned long long hit = __ballot(best == wp.v);
+                int jw = 0x7fffffff;
+                while (hit) {
+                    const int l = __ffsll((long long)hit) - 1;
+                    hit &= hit - 1ull;
+                    jw = min(jw, __builtin_amdgcn_readlane(bj, l));
+                }
+                wp.j = jw;
+            }
+            // the wave's line-search partials over its atoms, relative to wp.v
+            double rk[KA], vk[KA], ck[KA];
+            {
+                double p = 0.0, q2 = 0.0, tj = 0.0, ts = 0.0;
+#pragma unroll
+                for (int k = 0; k < KA; ++k) {
+                    const int qk = A.q[k] >= 0 ? A.q[k] : 0;
+                    rk[k] = r_lds[((qk >> 1) * NT + tid) * 2 + (qk & 1)];
+                    if constexpr (FUSED) ck[k] = sqdist(S.x[0], S.x[1], S.x[2], A.y[k][0], A.y[k][1], A.y[k][2]);
+                    else ck[k] = (double)A.c[k];
+                    vk[k] = ck[k] + w * rk[k];
+                    const double t = A.t[k];
+                    const bool at_j = A.q[k] >= 0 && owned_col<NT, VEC>(A.q[k], tid) == wp.j;
+                    p += t * (vk[k] - wp.v);
+                    q2 += at_j ? 0.0 : t * t;
+                    tj += at_j ? t : 0.0;
+                    ts += t;
+                }
+                const unsigned long long act = __ballot((mk != 0u) && (p != 0.0 || q2 != 0.0 || tj != 0.0 || ts != 0.0));
+                wp.P = lanes_sum(p, act);
+                wp.Q = lanes_sum(q2, act);
+                wp.tj = lanes_sum(tj, act);
+                wp.Ts = lanes_sum(ts, act);
+                wp.more = __any(more) ? 1 : 0;
+            }
+            // one exchange per step: merge the waves' partials in wave order
+            WavePart gp = wp;
+            if (NW > 1) {
+                if (lane == 0) s_part[s & 1][wid] = wp;
+                __syncthreads();
+                gp = s_part[s & 1][0];
+#pragma unroll
+                for (int k = 1; k < NW; ++k) gp = wave_part_merge(gp, s_part[s & 1][k]);
+            }
+            if (gp.more) { stop = true; done = s; break; }
+            const int jstar = gp.j;
+
+            // step size of Alg. 1, then t_i <- (1 - gamma) t_i + gamma a_i e_j*
+            // and r <- r + (t_i new - t_i old), on the support and at j*
+            const double gamma = step_size(rule, k0 + s, m, w, gp.P, gp.Q, gp.tj, ai);
+            const double gadd = gamma * ai;
+            const int jg = jstar / VEC;
+            const int us = ((jg % NT) == tid) ? (jg / NT) * VEC + (jstar % VEC) : -1;
+            uint32_t nm = mk;
+            const __amdgpu_buffer_rsrc_t rt = buf_rsrc(T + base, row_bytes);
+            double tn[KA];
+            bool star_in = false;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) {
+                const bool st = A.q[k] >= 0 && A.q[k] == us;
+                star_in |= st;
+                tn[k] = blend(A.t[k], gamma, st ? gadd : 0.0);
+                const bool put = A.q[k] >= 0 && tn[k] != A.t[k];
+                const int qk = A.q[k] >= 0 ? A.q[k] : 0;
+                if (put) r_lds[((qk >> 1) * NT + tid) * 2 + (qk & 1)] = rk[k] + (tn[k] - A.t[k]);
+                if (A.q[k] >= 0) nm = (tn[k] != 0.0) ? (nm | (1u << A.q[k])) : (nm & ~(1u << A.q[k]));
+                buf_store_f64(tn[k], rt, put ? (unsigned)owned_col<NT, VEC>(qk, tid) * 8u : kOOB);
+            }
+            const double tsn = blend(0.0, gamma, gadd);
+            const bool put_s = us >= 0 && !star_in && tsn != 0.0;
+            {
+                const int qs = us >= 0 ? us : 0;
+                if (put_s) {
+                    const int a_ = ((qs >> 1) * NT + tid) * 2 + (qs & 1);
+                    r_lds[a_] = r_lds[a_] + tsn;
+                    nm |= (1u << qs);
+                }
+                buf_store_f64(tsn, rt, put_s ? (unsigned)owned_col<NT, VEC>(qs, tid) * 8u : kOOB);
+            }
+            buf_store_u32(nm, buf_rsrc(M + (size_t)i * NT, NT * 4u), nm != mk ? (unsigned)tid * 4u : kOOB);
+            if constexpr (TRACE) {
+                const __amdgpu_buffer_rsrc_t rs_tj = buf_rsrc(trace_j, (unsigned)nsteps * 4u);
+                const __amdgpu_buffer_rsrc_t rs_tg = buf_rsrc(trace_gamma, (unsigned)nsteps * 8u);
+                buf_store_u32((unsigned)jstar, rs_tj, tid == 0 ? (unsigned)s * 4u : kOOB);
+                buf_store_f64(gamma, rs_tg, tid == 0 ? (unsigned)s * 8u : kOOB);
+            }
+
+            // the next step visits this row again: hand its new atoms over
+            if (ring[(slot + 1) % DA].i == i) {
+                F.mk = nm;
+                low_bits(nm, F.q);
+#pragma unroll
+                for (int k = 0; k < KA; ++k) {
+                    double tv = 0.0;
+                    CT cv = (CT)0;
+                    float yv0 = 0.f, yv1 = 0.f, yv2 = 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < KA; ++kk) {
+                        const bool hit = A.q[kk] >= 0 && A.q[kk] == F.q[k];
+                        tv = hit ? tn[kk] : tv;
+                        if constexpr (FUSED) {
+                            yv0 = hit ? A.y[kk][0] : yv0; yv1 = hit ? A.y[kk][1] : yv1; yv2 = hit ? A.y[kk][2] : yv2;
+                        } else {
+                            cv = hit ? A.c[kk] : cv;
+                        }
+                    }
+                    if (put_s && F.q[k] == us) {
+                        tv = tsn;
+#pragma unroll
+                        for (int u = 0; u < CPT; ++u) {
+                            if constexpr (FUSED) {
+                                yv0 = (u == us) ? y0[u] : yv0; yv1 = (u == us) ? y1[u] : yv1; yv2 = (u == us) ? y2[u] : yv2;
+                            } else {
+                                cv = (u == us) ? S.c[u] : cv;
+                            }
+                        }
+                    }
+                    F.t[k] = tv;
+                    if constexpr (FUSED) { F.y[k][0] = yv0; F.y[k][1] = yv1; F.y[k][2] = yv2; }
+                    else F.c[k] = cv;
+                }
+            }
+            f2i = f1i; f2m = f1m;
+            f1i = i; f1m = nm;
+
+            // atoms of step s + 2, on its mask patched by the last two updates
+            {
+                RowSlot<CPT, CT> &R = ring[(slot + 2) % DA];
+                const int ri = __builtin_amdgcn_readfirstlane(R.i);
+                const uint32_t rmk = (ri == f1i) ? f1m : ((ri == f2i) ? f2m : R.mk);
+                issue_atoms(at[slot & 1], ri, rmk);
+            }
+            // row of step s + DA, block index of step s + 2*DA
+            issue_row(ring[slot], nidx[slot]);
+            nidx[slot] = idxv[s + 2 * DA < last ? s + 2 * DA : last];
+        }
+        if (stop) break;
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int j = owned_col<NT, VEC>(u, tid);
+        if (j < n) rg[j] = r_lds[r_at(u)];
+    }
+    if (tid == 0) *resume = done;
+}
+
+template <int NT, int CPT, int VEC, int COST>
+__global__ __launch_bounds__(NT) void chain_tail_kernel(ProblemView P, double *__restrict__ T,
+                                                        double *__restrict__ rg,
+                                                        uint32_t *__restrict__ M,
+                                                        const int32_t *__restrict__ idx, int64_t k0,
+                                                        int64_t nsteps, int rule,
+                                                        int32_t *__restrict__ trace_j,
+                                                        double *__restrict__ trace_gamma,
+                                                        const int64_t *__restrict__ resume)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
+    constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NW = NT / 64;
-    __shared__ ArgPart sh[2][NW];
+    __shared__ double s_v[2][NW];
+    __shared__ int s_j[2][NW];
+    __shared__ double s_sum[2][NW][3];
     const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
     const double w = P.w;
     const CT *__restrict__ C = (const CT *)P.C;
+    const int64_t start = *resume;
+    if (start >= nsteps) return;
 
     double r[CPT];
-    float y0[CPT], y1[CPT], y2[CPT];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int j = q * NT + tid;
-        r[q] = (j < n) ? rg[j] : 0.0;
-        if constexpr (COST == SROT_COST_SQEUCLID) {
-            y0[q] = (j < n) ? P.Y[3 * j + 0] : 0.f;
-            y1[q] = (j < n) ? P.Y[3 * j + 1] : 0.f;
-            y2[q] = (j < n) ? P.Y[3 * j + 2] : 0.f;
-        }
+    for (int u = 0; u < CPT; ++u) {
+        const int j = owned_col<NT, VEC>(u, tid);
+        r[u] = (j < n) ? rg[j] : 0.0;
     }
-
-    CT c_cur[CPT], c_nxt[CPT];
-    double t_cur[CPT], t_nxt[CPT];
-    float x_cur[3] = {0.f, 0.f, 0.f}, x_nxt[3] = {0.f, 0.f, 0.f};
-
-    auto load_row = [&](int i, CT (&c)[CPT], double (&t)[CPT], float (&x)[3]) {
+    for (int64_t s = start; s < nsteps; ++s) {
+        const int i = idx[s];
+        const double ai = P.a[i];
         const size_t base = (size_t)i * (size_t)n;
+        const uint32_t mk = M[(size_t)i * NT + tid];
+        CT cv[CPT];
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
+        else load_cost_row<NT, CPT, VEC, CT>(C + base, n, tid, cv);
+        double t[CPT], vv[CPT];
+        double best = INFINITY;
+        int bj = 0x7fffffff;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int j = q * NT + tid;
-            if (j < n) {
-                if constexpr (COST != SROT_COST_SQEUCLID) c[q] = C[base + j];
-                t[q] = T[base + j];
-            } else {
-                if constexpr (COST != SROT_COST_SQEUCLID) c[q] = (CT)0;
-                t[q] = 0.0;
-            }
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            const int jc = j < n ? j : n - 1;
+            t[u] = (mk & (1u << u)) ? T[base + j] : 0.0;
+            double c;
+            if constexpr (FUSED) c = sqdist(x0, x1, x2, P.Y[3 * jc], P.Y[3 * jc + 1], P.Y[3 * jc + 2]);
+            else c = (double)cv[u];
+            vv[u] = c + w * r[u];
+            const double v = (j < n) ? vv[u] : INFINITY;
+            if (v < best) { best = v; bj = j; }
         }
-        if constexpr (COST == SROT_COST_SQEUCLID) {
-            x[0] = P.X[3 * i + 0]; x[1] = P.X[3 * i + 1]; x[2] = P.X[3 * i + 2];
-        }
-    };
-
-    int i_cur = idx[0];
-    load_row(i_cur, c_cur, t_cur, x_cur);
-
-    for (int64_t s = 0; s < nsteps; ++s) {
-        int i_nxt = i_cur;
-        if (s + 1 < nsteps) {
-            i_nxt = idx[s + 1];
-            load_row(i_nxt, c_nxt, t_nxt, x_nxt);
-        }
-        const double ai = P.a[i_cur];
-
-        // block gradient c_i + w r (eq. RelaxedGradient) and the partial LMO
-        ArgPart p;
-        part_init(p);
+        block_argmin<NW>(best, bj, s_v[s & 1], s_j[s & 1]);
+        const double G = best;
+        const int jstar = bj;
+        double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int j = q * NT + tid;
-            if (j < n) {
-                double c;
-                if constexpr (COST == SROT_COST_SQEUCLID)
-                    c = sqdist(x_cur[0], x_cur[1], x_cur[2], y0[q], y1[q], y2[q]);
-                else
-                    c = (double)c_cur[q];
-                part_push(p, c + w * r[q], t_cur[q], j);
-            }
+        for (int u = 0; u < CPT; ++u) {
+            const bool st = (owned_col<NT, VEC>(u, tid) == jstar);
+            acc[0] += t[u] * (vv[u] - G);
+            acc[1] += st ? 0.0 : t[u] * t[u];
+            acc[2] = st ? t[u] : acc[2];
         }
-        const ArgPart res = block_reduce<NW>(p, sh[s & 1]);
-        const double gamma = step_size(rule, k0 + s, m, w, res, ai);
-
-        // t_i <- (1 - gamma) t_i + gamma a_i e_j*;  r <- r + (t_i new - t_i old)
-        const size_t base = (size_t)i_cur * (size_t)n;
+        block_sum<NW, 3>(acc, s_sum[s & 1]);
+        const double gamma = step_size(rule, k0 + s, m, w, acc[0], acc[1], acc[2], ai);
+        const double gadd = gamma * ai;
+        const int jg = jstar / VEC;
+        const int us = ((jg % NT) == tid) ? (jg / NT) * VEC + (jstar % VEC) : -1;
+        uint32_t nm = 0u;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int j = q * NT + tid;
-            if (j < n) {
-                const double sv = (j == res.j) ? ai : 0.0;
-                const double tn = (1.0 - gamma) * t_cur[q] + gamma * sv;
-                r[q] += tn - t_cur[q];
-                if (tn != t_cur[q]) T[base + j] = tn;
-                t_cur[q] = tn;
-            }
+        for (int u = 0; u < CPT; ++u) {
+            const double tn = blend(t[u], gamma, (u == us) ? gadd : 0.0);
+            if (tn != t[u]) T[base + owned_col<NT, VEC>(u, tid)] = tn;
+            r[u] += tn - t[u];
+            nm |= (tn != 0.0) ? (1u << u) : 0u;
         }
+        if (nm != mk) M[(size_t)i * NT + tid] = nm;
         if (tid == 0) {
-            if (trace_j) trace_j[s] = res.j;
+            if (trace_j) trace_j[s] = jstar;
             if (trace_gamma) trace_gamma[s] = gamma;
         }
-        // the prefetched copy of a row updated in this step is stale
-        if (s + 1 < nsteps) {
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                if (i_nxt == i_cur) t_nxt[q] = t_cur[q];
-                t_cur[q] = t_nxt[q];
-                if constexpr (COST != SROT_COST_SQEUCLID) c_cur[q] = c_nxt[q];
-            }
-            x_cur[0] = x_nxt[0]; x_cur[1] = x_nxt[1]; x_cur[2] = x_nxt[2];
-            i_cur = i_nxt;
-        }
     }
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int j = q * NT + tid;
-        if (j < n) rg[j] = r[q];
+    for (int u = 0; u < CPT; ++u) {
+        const int j = owned_col<NT, VEC>(u, tid);
+        if (j < n) rg[j] = r[u];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Block-step chain for any n: r in global memory, column j owned by thread
-// j mod GLB_NT for reads and writes, so no cross-thread hazard on r or T.
+// Block-step chain for wide rows: r in global memory; thread tid owns columns
+// j = u * GLB_NT + tid for all u, reads and writes only those entries of r,
+// T and its mask words.
 // ---------------------------------------------------------------------------
 constexpr int GLB_NT = 512;
 
 template <int COST>
 __global__ __launch_bounds__(GLB_NT) void chain_glb_kernel(ProblemView P, double *__restrict__ T,
-                                                         double *__restrict__ rg,
-                                                         const int32_t *__restrict__ idx,
-                                                         int64_t k0, int64_t nsteps, int rule,
-                                                         int32_t *__restrict__ trace_j,
-                                                         double *__restrict__ trace_gamma)
+                                                           double *__restrict__ rg,
+                                                           uint32_t *__restrict__ M, int words,
+                                                           const int32_t *__restrict__ idx,
+                                                           int64_t k0, int64_t nsteps, int rule,
+                                                           int32_t *__restrict__ trace_j,
+                                                           double *__restrict__ trace_gamma)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
+    constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NT = GLB_NT, NW = NT / 64;
-    __shared__ ArgPart sh[2][NW];
+    __shared__ double s_v[2][NW];
+    __shared__ int s_j[2][NW];
+    __shared__ double s_sum[2][NW][4];
     const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
     const double w = P.w;
     const CT *__restrict__ C = (const CT *)P.C;
+
+    auto cost = [&](int i, int j, float x0, float x1, float x2) -> double {
+        if constexpr (FUSED) return sqdist(x0, x1, x2, P.Y[3 * j], P.Y[3 * j + 1], P.Y[3 * j + 2]);
+        else return (double)C[(size_t)i * (size_t)n + j];
+    };
 
     for (int64_t s = 0; s < nsteps; ++s) {
         const int i = idx[s];
         const double ai = P.a[i];
         const size_t base = (size_t)i * (size_t)n;
         float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-        if constexpr (COST == SROT_COST_SQEUCLID) {
-            x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2];
-        }
-        ArgPart p;
-        part_init(p);
+        if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
+        double best = INFINITY;
+        int bj = 0x7fffffff;
         for (int j = tid; j < n; j += NT) {
-            double c;
-            if constexpr (COST == SROT_COST_SQEUCLID)
-                c = sqdist(x0, x1, x2, P.Y[3 * j], P.Y[3 * j + 1], P.Y[3 * j + 2]);
-            else
-                c = (double)C[base + j];
-            part_push(p, c + w * rg[j], T[base + j], j);
+            const double v = cost(i, j, x0, x1, x2) + w * rg[j];
+            if (v < best) { best = v; bj = j; }
         }
-        const ArgPart res = block_reduce<NW>(p, sh[s & 1]);
-        const double gamma = step_size(rule, k0 + s, m, w, res, ai);
-        for (int j = tid; j < n; j += NT) {
-            const double t = T[base + j];
-            const double sv = (j == res.j) ? ai : 0.0;
-            const double tn = (1.0 - gamma) * t + gamma * sv;
-            if (tn != t) {
-                T[base + j] = tn;
-                rg[j] += tn - t;
+        block_argmin<NW>(best, bj, s_v[s & 1], s_j[s & 1]);
+        const double G = best;
+        const int jstar = bj;
+
+        uint32_t *Mi = M + (size_t)i * words * NT + tid;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int wd = 0; wd < words; ++wd) {
+            uint32_t mk = Mi[(size_t)wd * NT];
+            while (mk) {
+                const int b = __ffs(mk) - 1;
+                mk &= mk - 1u;
+                const int j = (wd * 32 + b) * NT + tid;
+                const double t = T[base + j];
+                const double v = cost(i, j, x0, x1, x2) + w * rg[j];
+                acc[0] += t * (v - G);
+                if (j == jstar) acc[2] = t;
+                else acc[1] += t * t;
             }
         }
+        block_sum<NW, 4>(acc, s_sum[s & 1]);
+        const double gamma = step_size(rule, k0 + s, m, w, acc[0], acc[1], acc[2], ai);
+
+        for (int wd = 0; wd < words; ++wd) {
+            const uint32_t mk = Mi[(size_t)wd * NT];
+            uint32_t nm = mk, todo = mk;
+            const int ustar = jstar / NT - wd * 32;
+            const bool st_here = (jstar % NT) == tid && ustar >= 0 && ustar < 32;
+            if (st_here) todo |= (1u << ustar);
+            while (todo) {
+                const int b = __ffs(todo) - 1;
+                todo &= todo - 1u;
+                const int j = (wd * 32 + b) * NT + tid;
+                const bool on = (mk >> b) & 1u;
+                const double told = on ? T[base + j] : 0.0;
+                const double tn = (1.0 - gamma) * told + ((j == jstar) ? gamma * ai : 0.0);
+                if (tn != told) {
+                    T[base + j] = tn;
+                    rg[j] += tn - told;
+                }
+                nm = (tn != 0.0) ? (nm | (1u << b)) : (nm & ~(1u << b));
+            }
+            if (nm != mk) Mi[(size_t)wd * NT] = nm;
+        }
         if (tid == 0) {
-            if (trace_j) trace_j[s] = res.j;
+            if (trace_j) trace_j[s] = jstar;
             if (trace_gamma) trace_gamma[s] = gamma;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Gap sweep (Thm 2, eq. AppenEq:Gi, dual of App. D).  One wave per row:
+// Gap sweep (Thm 2, eq. AppenEq:Gi, dual of App. D).  One workgroup handles
+// one row at a time with the handle's column ownership:
 //   G_i = min_j v_ij (lowest argmin j*_i),  g_i = sum_j t_ij (v_ij - G_i),
-//   lin_i = sum_j t_ij c_ij.
-// Per block: sums of a_i G_i, lin_i and g_i, in row order per wave and wave
-// order per block; gap_final_kernel adds the blocks in order.
+//   lin_i = sum_j t_ij c_ij   (sums over the support only).
+// Thread 0 accumulates a_i G_i, lin_i and g_i over its rows in row order;
+// gap_final_kernel adds the workgroups in order.
+// CPT > 0: r held in registers (n <= NT * CPT); CPT == 0: r read from memory
+// (VEC must be 1 then).
 // ---------------------------------------------------------------------------
-struct GapPart {
-    double v, P, Ts, lin;
-    int j;
-};
-
-__device__ __forceinline__ void gpart_push(GapPart &p, double v, double t, double c, int j)
-{
-    if (v < p.v) {
-        if (p.Ts != 0.0) p.P += (p.v - v) * p.Ts;
-        p.v = v; p.j = j;
-    } else {
-        p.P += t * (v - p.v);
-    }
-    p.Ts += t;
-    p.lin += t * c;
-}
-
-__device__ __forceinline__ GapPart gpart_merge(const GapPart &A, const GapPart &B)
-{
-    const bool bw = (B.v < A.v) || (B.v == A.v && B.j < A.j);
-    const GapPart &W = bw ? B : A;
-    GapPart o;
-    o.v = W.v; o.j = W.j;
-    const double pa = (A.Ts != 0.0) ? (A.v - W.v) * A.Ts : 0.0;
-    const double pb = (B.Ts != 0.0) ? (B.v - W.v) * B.Ts : 0.0;
-    o.P = (A.P + B.P) + (pa + pb);
-    o.Ts = A.Ts + B.Ts;
-    o.lin = A.lin + B.lin;
-    return o;
-}
-
-constexpr int GAP_NT = 256;
-
-template <int COST>
-__global__ __launch_bounds__(GAP_NT) void gap_kernel(ProblemView P, const double *__restrict__ T,
-                                                     const double *__restrict__ rg,
-                                                     double *__restrict__ row_G,
-                                                     int32_t *__restrict__ row_j,
-                                                     double *__restrict__ row_g,
-                                                     double *__restrict__ partials)
+template <int NT, int CPT, int VEC, int COST>
+__global__ __launch_bounds__(NT) void gap_kernel(ProblemView P, const double *__restrict__ T,
+                                                 const double *__restrict__ rg,
+                                                 const uint32_t *__restrict__ M, int words,
+                                                 double *__restrict__ row_G,
+                                                 int32_t *__restrict__ row_j,
+                                                 double *__restrict__ row_g,
+                                                 double *__restrict__ partials)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
-    constexpr int NW = GAP_NT / 64;
-    __shared__ double sh[NW][3];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
+    constexpr int NW = NT / 64;
+    constexpr int RC = CPT > 0 ? CPT : 1;
+    __shared__ double s_v[2][NW];
+    __shared__ int s_j[2][NW];
+    __shared__ double s_sum[2][NW][2];
+    const int tid = threadIdx.x;
     const int n = P.n, m = P.m;
     const double w = P.w;
     const CT *__restrict__ C = (const CT *)P.C;
-    const int gw = blockIdx.x * NW + wid;
-    const int nw_total = gridDim.x * NW;
+
+    double r[RC];
+    if constexpr (CPT > 0) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            r[u] = (j < n) ? rg[j] : 0.0;
+        }
+    }
+    auto cost = [&](int i, int j, float x0, float x1, float x2) -> double {
+        if constexpr (FUSED) return sqdist(x0, x1, x2, P.Y[3 * j], P.Y[3 * j + 1], P.Y[3 * j + 2]);
+        else return (double)C[(size_t)i * (size_t)n + j];
+    };
 
     double acc_aG = 0.0, acc_lin = 0.0, acc_g = 0.0;
-    for (int i = gw; i < m; i += nw_total) {
-        const size_t base = (size_t)i * (size_t)n;
+    int par = 0;
+    for (int i = blockIdx.x; i < m; i += gridDim.x, par ^= 1) {
         float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-        if constexpr (COST == SROT_COST_SQEUCLID) {
-            x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2];
-        }
-        GapPart p;
-        p.v = INFINITY; p.P = 0.0; p.Ts = 0.0; p.lin = 0.0; p.j = 0x7fffffff;
-        for (int j = lane; j < n; j += 64) {
-            double c;
-            if constexpr (COST == SROT_COST_SQEUCLID)
-                c = sqdist(x0, x1, x2, P.Y[3 * j], P.Y[3 * j + 1], P.Y[3 * j + 2]);
-            else
-                c = (double)C[base + j];
-            gpart_push(p, c + w * rg[j], T[base + j], c, j);
-        }
+        if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
+        double best = INFINITY;
+        int bj = 0x7fffffff;
+        if constexpr (CPT > 0) {
+            CT cv[RC];
+            if constexpr (!FUSED) load_cost_row<NT, CPT, VEC, CT>(C + (size_t)i * (size_t)n, n, tid, cv);
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            GapPart o;
-            o.v = __shfl_xor(p.v, off);
-            o.P = __shfl_xor(p.P, off);
-            o.Ts = __shfl_xor(p.Ts, off);
-            o.lin = __shfl_xor(p.lin, off);
-            o.j = __shfl_xor(p.j, off);
-            p = gpart_merge(p, o);
+            for (int u = 0; u < CPT; ++u) {
+                const int j = owned_col<NT, VEC>(u, tid);
+                double c;
+                if constexpr (FUSED) c = (j < n) ? cost(i, j, x0, x1, x2) : 0.0;
+                else c = (double)cv[u];
+                const double v = (j < n) ? c + w * r[u] : INFINITY;
+                if (v < best) { best = v; bj = j; }
+            }
+        } else {
+            for (int j = tid; j < n; j += NT) {
+                const double v = cost(i, j, x0, x1, x2) + w * rg[j];
+                if (v < best) { best = v; bj = j; }
+            }
         }
-        if (lane == 0) {
-            row_G[i] = p.v;
-            row_j[i] = p.j;
-            row_g[i] = p.P;
-            acc_aG += P.a[i] * p.v;
-            acc_lin += p.lin;
-            acc_g += p.P;
+        block_argmin<NW>(best, bj, s_v[par], s_j[par]);
+        const double G = best;
+
+        double acc[2] = {0.0, 0.0};  // g_i, lin_i
+        const uint32_t *Mi = M + (size_t)i * words * NT + tid;
+        const size_t base = (size_t)i * (size_t)n;
+        for (int wd = 0; wd < words; ++wd) {
+            uint32_t mk = Mi[(size_t)wd * NT];
+            while (mk) {
+                const int b = __ffs(mk) - 1;
+                mk &= mk - 1u;
+                const int u = wd * 32 + b;
+                int j;
+                double rj;
+                if constexpr (CPT > 0) {
+                    j = owned_col<NT, VEC>(u, tid);
+                    rj = 0.0;
+#pragma unroll
+                    for (int q = 0; q < CPT; ++q) rj = (q == u) ? r[q] : rj;
+                } else {
+                    j = u * NT + tid;
+                    rj = rg[j];
+                }
+                const double t = T[base + j];
+                const double c = cost(i, j, x0, x1, x2);
+                acc[0] += t * (c + w * rj - G);
+                acc[1] += t * c;
+            }
+        }
+        block_sum<NW, 2>(acc, s_sum[par]);
+        if (tid == 0) {
+            row_G[i] = G;
+            row_j[i] = bj;
+            row_g[i] = acc[0];
+            acc_aG += P.a[i] * G;
+            acc_lin += acc[1];
+            acc_g += acc[0];
         }
     }
-    if (lane == 0) {
-        sh[wid][0] = acc_aG; sh[wid][1] = acc_lin; sh[wid][2] = acc_g;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int k = 0; k < NW; ++k) { s0 += sh[k][0]; s1 += sh[k][1]; s2 += sh[k][2]; }
-        partials[4 * blockIdx.x + 0] = s0;
-        partials[4 * blockIdx.x + 1] = s1;
-        partials[4 * blockIdx.x + 2] = s2;
+    if (tid == 0) {
+        partials[4 * blockIdx.x + 0] = acc_aG;
+        partials[4 * blockIdx.x + 1] = acc_lin;
+        partials[4 * blockIdx.x + 2] = acc_g;
     }
 }
 
@@ -479,7 +1037,7 @@ __global__ __launch_bounds__(256) void gap_final_kernel(ProblemView P, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Initial plan t_i = a_i e_0, residual, validation.
+// Initial plan t_i = a_i e_0, residual, support masks, validation.
 // ---------------------------------------------------------------------------
 __global__ void init_plan_kernel(int32_t m, int32_t n, const double *__restrict__ a,
                                  double *__restrict__ T)
@@ -492,6 +1050,13 @@ __global__ void init_plan_kernel(int32_t m, int32_t n, const double *__restrict_
     }
 }
 
+// Target points padded to 16 bytes (one vector load per point).
+__global__ void pad_points_kernel(int32_t n, const float *__restrict__ Y, float4 *__restrict__ Y4)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        Y4[j] = make_float4(Y[3 * j], Y[3 * j + 1], Y[3 * j + 2], 0.f);
+}
+
 // r_j = sum_i T_ij - b_j, rows added in order.
 __global__ void residual_kernel(int32_t m, int32_t n, const double *__restrict__ T,
                                 const double *__restrict__ b, double *__restrict__ r)
@@ -501,6 +1066,25 @@ __global__ void residual_kernel(int32_t m, int32_t n, const double *__restrict__
     double s = 0.0;
     for (int i = 0; i < m; ++i) s += T[(size_t)i * (size_t)n + j];
     r[j] = s - b[j];
+}
+
+// Support masks from a dense plan, in the layout of Ownership.
+__global__ void mask_build_kernel(int32_t m, int32_t n, Ownership own, const double *__restrict__ T,
+                                  uint32_t *__restrict__ M)
+{
+    const int tid = threadIdx.x;  // blockDim.x == own.nt
+    for (int i = blockIdx.x; i < m; i += gridDim.x) {
+        const size_t base = (size_t)i * (size_t)n;
+        for (int wd = 0; wd < own.words; ++wd) {
+            uint32_t word = 0u;
+            for (int b = 0; b < 32; ++b) {
+                const int u = wd * 32 + b;
+                const int j = ((u / own.vec) * own.nt + tid) * own.vec + (u % own.vec);
+                if (u < own.cpt && j < n && T[base + j] != 0.0) word |= (1u << b);
+            }
+            M[((size_t)i * own.words + wd) * own.nt + tid] = word;
+        }
+    }
 }
 
 template <typename V>
@@ -603,7 +1187,7 @@ __global__ __launch_bounds__(256) void sample_permute_kernel(uint64_t seed, int6
 }
 
 // ---------------------------------------------------------------------------
-// Launch wrappers
+// Variant choice and launch wrappers
 // ---------------------------------------------------------------------------
 static int grid_for(size_t work, int nt, int cap)
 {
@@ -611,6 +1195,66 @@ static int grid_for(size_t work, int nt, int cap)
     if (g < 1) g = 1;
     if (g > (size_t)cap) g = cap;
     return (int)g;
+}
+
+#define SROT_VARIANTS_V1(X) \
+    X(64, 2, 1) X(64, 4, 1) X(128, 4, 1) X(256, 4, 1) X(256, 8, 1) X(256, 16, 1) X(512, 8, 1)
+#define SROT_VARIANTS_V2(X) \
+    X(64, 2, 2) X(64, 4, 2) X(128, 4, 2) X(256, 4, 2) X(256, 8, 2) X(256, 16, 2) X(512, 8, 2)
+#define SROT_VARIANTS_V4(X) \
+    X(64, 4, 4) X(128, 4, 4) X(256, 4, 4) X(256, 8, 4) X(256, 16, 4) X(512, 8, 4)
+
+static bool variant_exists(int nt, int cpt, int vec)
+{
+    bool ok = false;
+#define SROT_HAS(NT_, CPT_, VEC_) ok |= (nt == NT_ && cpt == CPT_ && vec == VEC_);
+    SROT_VARIANTS_V1(SROT_HAS)
+    SROT_VARIANTS_V2(SROT_HAS)
+    SROT_VARIANTS_V4(SROT_HAS)
+#undef SROT_HAS
+    return ok;
+}
+
+// Default: the fewest threads with at most 16 columns each (rows up to 4096
+// columns keep r in registers), 16-byte cost loads when the row length and
+// alignment allow; wider rows take the global-residual kernel.
+// SROT_CHAIN_VARIANT=<nt>x<cpt>[x<vec>] overrides the choice when valid.
+Ownership choose_ownership(int64_t n, int cost, bool aligned16)
+{
+    int pref = cost == SROT_COST_F32 ? 4 : (cost == SROT_COST_F64 ? 2 : 1);
+    if (n % pref != 0 || !aligned16) pref = 1;
+    int nt = 0, cpt = 0, vec = 1;
+    const char *env = getenv("SROT_CHAIN_VARIANT");
+    if (env) {
+        int a = 0, b = 0, c = 1;
+        const int got = sscanf(env, "%dx%dx%d", &a, &b, &c);
+        if (got >= 2) {
+            if (got == 2) c = (b % pref == 0) ? pref : 1;
+            if (n <= (int64_t)a * b && (c == 1 || c == pref) && variant_exists(a, b, c)) {
+                nt = a; cpt = b; vec = c;
+            }
+        }
+    }
+    if (nt == 0) {
+        if (n <= 128) { nt = 64; cpt = 2; }
+        else if (n <= 256) { nt = 64; cpt = 4; }
+        else if (n <= 512) { nt = 128; cpt = 4; }
+        else if (n <= 1024) { nt = 256; cpt = 4; }
+        else if (n <= 2048) { nt = 256; cpt = 8; }
+        else if (n <= 4096) { nt = 256; cpt = 16; }
+        if (nt > 0) vec = (cpt % pref == 0 && variant_exists(nt, cpt, pref)) ? pref : 1;
+    }
+    Ownership o;
+    if (nt > 0) {
+        o.nt = nt; o.cpt = cpt; o.vec = vec; o.words = 1; o.reg = 1;
+    } else {
+        o.nt = GLB_NT;
+        o.cpt = (int32_t)((n + GLB_NT - 1) / GLB_NT);
+        o.vec = 1;
+        o.words = (o.cpt + 31) / 32;
+        o.reg = 0;
+    }
+    return o;
 }
 
 hipError_t launch_validate(const ProblemView &P, const DeviceState &S, hipStream_t stream)
@@ -644,6 +1288,22 @@ hipError_t launch_residual(const ProblemView &P, const DeviceState &S, hipStream
     return hipGetLastError();
 }
 
+hipError_t launch_pad_points(const ProblemView &P, hipStream_t stream)
+{
+    if (!P.Y || !P.Y4) return hipSuccess;
+    hipLaunchKernelGGL(pad_points_kernel, dim3(grid_for((size_t)P.n, 256, 1024)), dim3(256), 0, stream,
+                       P.n, P.Y, const_cast<float4 *>(P.Y4));
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_build(const ProblemView &P, const DeviceState &S, hipStream_t stream)
+{
+    const int grid = P.m < 4096 ? P.m : 4096;
+    hipLaunchKernelGGL(mask_build_kernel, dim3(grid), dim3(S.own.nt), 0, stream, P.m, P.n, S.own,
+                       S.T, S.mask);
+    return hipGetLastError();
+}
+
 hipError_t launch_sample_uniform(uint64_t seed, int64_t k0, int64_t count, int32_t m,
                                  int32_t *out, hipStream_t stream)
 {
@@ -660,60 +1320,36 @@ hipError_t launch_sample_permute(uint64_t seed, int64_t p0, int64_t npasses, int
     return hipGetLastError();
 }
 
-// Register-resident variants (NT threads x CPT columns per thread).
-struct ChainVariant {
-    int nt, cpt;
-};
-static const ChainVariant kChainVariants[] = {
-    {64, 1}, {64, 2}, {64, 4}, {128, 4}, {256, 4}, {256, 8}, {256, 16}, {512, 8},
-};
-
-// Default choice: the fewest threads with at most 16 columns each, except
-// that small rows keep one wave.  SROT_CHAIN_VARIANT=<nt>x<cpt> overrides it
-// (used by the tuner); n above 4096 takes the global-residual kernel.
-static ChainVariant pick_chain_variant(int n)
-{
-    const char *env = getenv("SROT_CHAIN_VARIANT");
-    if (env) {
-        int nt = 0, cpt = 0;
-        if (sscanf(env, "%dx%d", &nt, &cpt) == 2) {
-            for (const ChainVariant &v : kChainVariants)
-                if (v.nt == nt && v.cpt == cpt && n <= nt * cpt) return v;
-        }
-    }
-    if (n <= 64) return {64, 1};
-    if (n <= 128) return {64, 2};
-    if (n <= 256) return {64, 4};
-    if (n <= 512) return {128, 4};
-    if (n <= 1024) return {256, 4};
-    if (n <= 2048) return {256, 8};
-    if (n <= 4096) return {256, 16};
-    return {0, 0};
-}
-
 template <int COST>
 static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, const int32_t *idx,
                                     int64_t k0, int64_t nsteps, int rule, int32_t *tj, double *tg,
                                     hipStream_t st)
 {
-    const ChainVariant v = pick_chain_variant(P.n);
-#define SROT_CHAIN(NT_, CPT_)                                                                      \
-    if (v.nt == NT_ && v.cpt == CPT_) {                                                            \
-        hipLaunchKernelGGL((chain_reg_kernel<NT_, CPT_, COST>), dim3(1), dim3(NT_), 0, st, P, S.T,   \
-                           S.r, idx, k0, nsteps, rule, tj, tg);                                    \
-        return hipGetLastError();                                                                  \
-    }
-    SROT_CHAIN(64, 1)
-    SROT_CHAIN(64, 2)
-    SROT_CHAIN(64, 4)
-    SROT_CHAIN(128, 4)
-    SROT_CHAIN(256, 4)
-    SROT_CHAIN(256, 8)
-    SROT_CHAIN(256, 16)
-    SROT_CHAIN(512, 8)
+    const Ownership &o = S.own;
+    if (o.reg) {
+#define SROT_CHAIN(NT_, CPT_, VEC_)                                                                \
+        if (o.nt == NT_ && o.cpt == CPT_ && o.vec == VEC_) {                                       \
+            if (tj || tg)                                                                          \
+                hipLaunchKernelGGL((chain_kernel<NT_, CPT_, VEC_, COST, true>), dim3(1), dim3(NT_), 0, \
+                                   st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.resume); \
+            else                                                                                   \
+                hipLaunchKernelGGL((chain_kernel<NT_, CPT_, VEC_, COST, false>), dim3(1), dim3(NT_),  \
+                                   0, st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg,       \
+                                   S.resume);                                                      \
+            hipError_t e_ = hipGetLastError();                                                     \
+            if (e_ != hipSuccess) return e_;                                                       \
+            hipLaunchKernelGGL((chain_tail_kernel<NT_, CPT_, VEC_, COST>), dim3(1), dim3(NT_), 0,    \
+                               st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.resume);  \
+            return hipGetLastError();                                                              \
+        }
+        SROT_VARIANTS_V1(SROT_CHAIN)
+        if constexpr (COST == SROT_COST_F32) { SROT_VARIANTS_V4(SROT_CHAIN) }
+        if constexpr (COST == SROT_COST_F64) { SROT_VARIANTS_V2(SROT_CHAIN) }
 #undef SROT_CHAIN
-    hipLaunchKernelGGL((chain_glb_kernel<COST>), dim3(1), dim3(GLB_NT), 0, st, P, S.T, S.r, idx, k0,
-                       nsteps, rule, tj, tg);
+        return hipErrorInvalidConfiguration;
+    }
+    hipLaunchKernelGGL((chain_glb_kernel<COST>), dim3(1), dim3(GLB_NT), 0, st, P, S.T, S.r, S.mask,
+                       o.words, idx, k0, nsteps, rule, tj, tg);
     return hipGetLastError();
 }
 
@@ -734,34 +1370,46 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
 
 int32_t gap_blocks_for(int64_t m)
 {
-    // one wave per row, 4 waves per block; at most 2048 blocks (8 per CU)
-    int64_t b = (m + 3) / 4;
+    int64_t b = m;
     if (b < 1) b = 1;
     if (b > 2048) b = 2048;
     return (int32_t)b;
 }
 
+template <int COST>
+static hipError_t launch_gap_cost(const ProblemView &P, const DeviceState &S, hipStream_t st)
+{
+    const Ownership &o = S.own;
+    const int nb = S.gap_blocks;
+    if (o.reg) {
+#define SROT_GAP(NT_, CPT_, VEC_)                                                                  \
+        if (o.nt == NT_ && o.cpt == CPT_ && o.vec == VEC_) {                                       \
+            hipLaunchKernelGGL((gap_kernel<NT_, CPT_, VEC_, COST>), dim3(nb), dim3(NT_), 0, st, P,   \
+                               S.T, S.r, S.mask, o.words, S.row_G, S.row_j, S.row_g, S.partials);  \
+            return hipGetLastError();                                                              \
+        }
+        SROT_VARIANTS_V1(SROT_GAP)
+        if constexpr (COST == SROT_COST_F32) { SROT_VARIANTS_V4(SROT_GAP) }
+        if constexpr (COST == SROT_COST_F64) { SROT_VARIANTS_V2(SROT_GAP) }
+#undef SROT_GAP
+        return hipErrorInvalidConfiguration;
+    }
+    hipLaunchKernelGGL((gap_kernel<GLB_NT, 0, 1, COST>), dim3(nb), dim3(GLB_NT), 0, st, P, S.T, S.r,
+                       S.mask, o.words, S.row_G, S.row_j, S.row_g, S.partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream)
 {
-    const int nb = S.gap_blocks;
+    hipError_t e;
     switch (P.cost) {
-    case SROT_COST_F32:
-        hipLaunchKernelGGL(gap_kernel<SROT_COST_F32>, dim3(nb), dim3(GAP_NT), 0, stream, P, S.T, S.r,
-                           S.row_G, S.row_j, S.row_g, S.partials);
-        break;
-    case SROT_COST_F64:
-        hipLaunchKernelGGL(gap_kernel<SROT_COST_F64>, dim3(nb), dim3(GAP_NT), 0, stream, P, S.T, S.r,
-                           S.row_G, S.row_j, S.row_g, S.partials);
-        break;
-    default:
-        hipLaunchKernelGGL(gap_kernel<SROT_COST_SQEUCLID>, dim3(nb), dim3(GAP_NT), 0, stream, P, S.T,
-                           S.r, S.row_G, S.row_j, S.row_g, S.partials);
-        break;
+    case SROT_COST_F32: e = launch_gap_cost<SROT_COST_F32>(P, S, stream); break;
+    case SROT_COST_F64: e = launch_gap_cost<SROT_COST_F64>(P, S, stream); break;
+    default: e = launch_gap_cost<SROT_COST_SQEUCLID>(P, S, stream); break;
     }
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(256), 0, stream, P, S.r, S.partials, nb,
-                       S.scalars);
+    hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(256), 0, stream, P, S.r, S.partials,
+                       S.gap_blocks, S.scalars);
     return hipGetLastError();
 }
 

@@ -73,7 +73,7 @@ def load():
     L.srot_get_plan.restype = ctypes.c_int
     L.srot_get_state.argtypes = [_vp, ctypes.POINTER(_i64)]
     L.srot_get_state.restype = ctypes.c_int
-    L.srot_set_state.argtypes = [_vp, _vp, _i64]
+    L.srot_set_state.argtypes = [_vp, _vp, _vp, _i64]
     L.srot_set_state.restype = ctypes.c_int
     L.srot_destroy.argtypes = [_vp]
     L.srot_destroy.restype = None
@@ -147,8 +147,8 @@ def srot_get_state(h):
     return k.value
 
 
-def srot_set_state(h, T_in, k):
-    _check(load().srot_set_state(h, _ptr(T_in), k))
+def srot_set_state(h, T_in, k, r_in=None):
+    _check(load().srot_set_state(h, _ptr(T_in), _ptr(r_in), k))
 
 
 def srot_destroy(h):
@@ -206,8 +206,8 @@ class Solver:
     def k(self):
         return srot_get_state(self.h)
 
-    def set_state(self, T, k):
-        srot_set_state(self.h, T, k)
+    def set_state(self, T, k, r=None):
+        srot_set_state(self.h, T, k, r)
 
     def close(self):
         if self.h:

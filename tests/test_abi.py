@@ -38,8 +38,8 @@ def test_default_options_and_workspace_size():
     assert opt.w == 1.0 and opt.step_rule == S.SROT_ELS and opt.sampling == S.SROT_UNIFORM
     assert opt.eps == 1e-6 and opt.max_passes == 1000 and opt.gap_every == 1
     ws = S.srot_workspace_size(4096, 4096, opt)
-    # dense FP64 plan dominates: 128 MiB plus small buffers
-    assert 4096 * 4096 * 8 < ws < 4096 * 4096 * 8 + (8 << 20)
+    # dense FP64 plan dominates: 128 MiB plus support masks and small buffers
+    assert 4096 * 4096 * 8 < ws < 4096 * 4096 * 8 + (16 << 20)
     assert ws % 256 == 0
     assert S.srot_workspace_size(0, 5, opt) == 0
     assert S.srot_workspace_size(5, -1, opt) == 0

@@ -209,7 +209,12 @@ def test_zero_penalty_closed_form_on_gpu():
 
 def test_exact_ties_pick_lowest_column():
     _need_gpu()
-    # identical target points -> identical cost columns
+    # identical target points -> identical cost columns and equal b: while
+    # neither twin has been touched, r is exactly -b_j on both sides and the
+    # tie is exact, so the lowest column must win.  Once rounding separates the
+    # twins, either may win a later rounding-level tie with a nonzero step and
+    # the two runs continue on twin-swapped (equivalent) plans, so the traces
+    # are compared up to the first such divergence only.
     X = I.mixture_points(1, 40)
     Y = I.mixture_points(2, 30)
     Y[10:20] = Y[0:10]
@@ -223,11 +228,21 @@ def test_exact_ties_pick_lowest_column():
         otr = O.bcfw_steps(P, st, idx)
         sol = _gpu_problem(d, mode, 1.0)
         gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
-        # exact ties (margin exactly 0) must resolve to the lowest column
-        exact = otr[2] == 0.0
-        assert exact.any()
-        np.testing.assert_array_equal(gj.cpu().numpy()[exact], otr[0][exact])
-        _compare_traces(otr, gj, gg)
+        gjn = gj.cpu().numpy()
+        diff = np.nonzero(gjn != otr[0])[0]
+        first = int(diff[0]) if len(diff) else len(idx)
+        if first < len(idx):
+            assert otr[2][first] <= 1e-12          # diverged only at a tie
+        np.testing.assert_allclose(gg.cpu().numpy()[:first], otr[1][:first], rtol=0, atol=1e-9)
+        touched = {0}
+        checked = 0
+        for k in range(first):
+            tied = [c for c in otr.near[k] if c >= 0]
+            if otr[2][k] == 0.0 and not any(c in touched for c in tied):
+                assert gjn[k] == otr[0][k] == min(tied)
+                checked += 1
+            touched.add(int(otr[0][k]))
+        assert checked > 0
 
 
 def test_resume_from_checkpoint_repeats_the_run():
@@ -242,8 +257,9 @@ def test_resume_from_checkpoint_repeats_the_run():
     part.step(4 * m + 17)
     T_mid, _ = part.plan()
     k_mid = part.k
+    _, r_mid = part.plan()
     resumed = _gpu_problem(d, "stored", 1.0, seed=5)
-    resumed.set_state(T_mid, k_mid)
+    resumed.set_state(T_mid, k_mid, r_mid)
     resumed.step(10 * m - k_mid)
     T_res, r_res = resumed.plan()
     assert torch.equal(T_res, T_full)
