@@ -1,10 +1,12 @@
-"""Builds libsrot.so (HIP, gfx950) in-tree next to this file."""
+"""Builds libsrot.so (HIP, gfx950) in-tree next to this file, and the
+copy_calibrate program used to scale HBM traffic counters."""
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrot.so")
+CALIB = os.path.join(HERE, "copy_calibrate")
 SOURCES = ["srot_kernels.hip", "srot_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,6 +25,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    exe = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-o", CALIB + ".tmp", os.path.join(CSRC, "copy_calibrate.hip")]
+    if verbose:
+        print(" ".join(exe), flush=True)
+    subprocess.run(exe, check=True)
+    os.replace(CALIB + ".tmp", CALIB)
     return LIB
 
 
