@@ -155,6 +155,31 @@ int srot_get_plan(srot_handle *h, double *T_out, double *r_out);
 int srot_get_state(srot_handle *h, int64_t *k);
 int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64_t k);
 
+/* Gradients of the optimal value V = min f (the problem above) with respect
+ * to the inputs, evaluated at the handle's current plan T and scaled by
+ * grad_out (dL/dV of a caller's loss L).  The paper does not differentiate
+ * V; these are the envelope-theorem derivatives, i.e. the partial
+ * derivatives of the Lagrangian of App. D with the plan held fixed:
+ *     dC_ij = g t_ij,            db_j = -g w r_j,
+ *     da_i  = g min_j (c_ij + w r_j)   (the row multiplier at the optimum),
+ *     dX_i  = 2 g sum_j t_ij (x_i - y_j),   dY_j = 2 g sum_i t_ij (y_j - x_i),
+ * with g = grad_out.  They are exact at an optimal plan; at an iterate with
+ * duality gap G (srot_gap) the residual, hence db, is within
+ * sqrt(2 w G) * |g| in Euclidean norm of its optimal value.  dX and dY take
+ * c_ij = ||x_i - y_j||^2, the fused cost, and need X and Y at srot_init.
+ *   dC   device, m x n, float for SROT_COST_F32, double for SROT_COST_F64;
+ *        NULL to skip; must be NULL for SROT_COST_SQEUCLID.  Written densely
+ *        (zeros off the plan's support).
+ *   dX   device, m x 3 float, or NULL.      dY  device, n x 3 float, or NULL.
+ *   da   device, m double, or NULL (costs one gap sweep).
+ *   db   device, n double, or NULL.
+ * Sums run in FP64 in a fixed order (bit-reproducible).  Enqueues the work
+ * and returns without synchronising.
+ * Errors: SROT_EINVAL (NULL handle, non-finite grad_out, dC with the fused
+ * cost, dX/dY without points), SROT_EHIP. */
+int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *dY,
+                  double *da, double *db);
+
 /* Destroys the handle (host memory only; the caller frees its buffers). */
 void srot_destroy(srot_handle *h);
 

@@ -47,7 +47,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, resume, Y4, total;
+    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, resume, Y4, adj, total;
     int64_t idx_cap;
     int32_t gap_blocks;
 };
@@ -86,6 +86,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.resume = off; off = align_up(off + sizeof(int64_t));
     L.Y4 = off; off = align_up(off + 16 * (size_t)n);
+    L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
     L.total = off;
     return L;
 }
@@ -227,6 +228,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->S.scalars = (double *)(base + L.scalars);
     h->S.flags = (int32_t *)(base + L.flags);
     h->S.resume = (int64_t *)(base + L.resume);
+    h->S.adj_part = (double *)(base + L.adj);
 
     int rc = SROT_OK;
     int32_t flag = 0;
@@ -330,6 +332,20 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
         SROT_HIP(srot::launch_residual(h->P, h->S, h->stream));
     SROT_HIP(srot::launch_mask_build(h->P, h->S, h->stream));
     h->k = k;
+    return SROT_OK;
+}
+
+int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *dY, double *da,
+                  double *db)
+{
+    if (!h) return fail(SROT_EINVAL, "srot_backward: NULL handle");
+    if (!isfinite(grad_out)) return fail(SROT_EINVAL, "srot_backward: grad_out is not finite");
+    if (dC && h->P.cost == SROT_COST_SQEUCLID)
+        return fail(SROT_EINVAL, "srot_backward: dC needs a stored cost (the fused cost has no C)");
+    if ((dX || dY) && (!h->P.X || !h->P.Y))
+        return fail(SROT_EINVAL, "srot_backward: dX and dY need the points X and Y given to srot_init");
+    if (da) SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));  // row minima of the gradient
+    SROT_HIP(srot::launch_adjoint(h->P, h->S, grad_out, dC, dX, dY, da, db, h->stream));
     return SROT_OK;
 }
 

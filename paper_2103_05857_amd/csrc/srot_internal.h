@@ -51,6 +51,7 @@ struct DeviceState {
     double *scalars;       // 8: g, f, D, ...
     int32_t *flags;        // 8: [0] validation/index error flag
     int64_t *resume;       // step at which the prefetching chain kernel stopped
+    double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
 };
 
 // Ownership chosen for an n-column problem with the given cost storage;
@@ -78,5 +79,13 @@ hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t st
 
 // Number of workgroups used by the gap sweep for an m-row problem.
 int32_t gap_blocks_for(int64_t m);
+
+// Adjoint at the current plan (srot_adjoint.hip): dC (m x n, float or double
+// as the stored cost), dX (m x 3), dY (n x 3), da (m, reads row_G of the last
+// gap sweep), db (n); each may be null.  g scales every output.
+hipError_t launch_adjoint(const ProblemView &P, const DeviceState &S, double g, void *dC,
+                          float *dX, float *dY, double *da, double *db, hipStream_t stream);
+// Row slices of the adjoint's column sums (sizes DeviceState::adj_part).
+int32_t adjoint_slices_cap(int64_t m);
 
 }  // namespace srot

@@ -75,6 +75,8 @@ def load():
     L.srot_get_state.restype = ctypes.c_int
     L.srot_set_state.argtypes = [_vp, _vp, _vp, _i64]
     L.srot_set_state.restype = ctypes.c_int
+    L.srot_backward.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+    L.srot_backward.restype = ctypes.c_int
     L.srot_destroy.argtypes = [_vp]
     L.srot_destroy.restype = None
     L.srot_strerror.argtypes = [ctypes.c_int]
@@ -151,6 +153,10 @@ def srot_set_state(h, T_in, k, r_in=None):
     _check(load().srot_set_state(h, _ptr(T_in), _ptr(r_in), k))
 
 
+def srot_backward(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):
+    _check(load().srot_backward(h, float(grad_out), _ptr(dC), _ptr(dX), _ptr(dY), _ptr(da), _ptr(db)))
+
+
 def srot_destroy(h):
     if h:
         load().srot_destroy(h)
@@ -208,6 +214,27 @@ class Solver:
 
     def set_state(self, T, k, r=None):
         srot_set_state(self.h, T, k, r)
+
+    def backward(self, grad_out=1.0, dC=False, dX=False, dY=False, da=False, db=False):
+        """Gradients of the optimal value at the current plan (srot_backward),
+        as a dict of the requested tensors."""
+        dev = self.workspace.device
+        m, n = self.m, self.n
+        out = {}
+        if dC:
+            cdt = torch.float64 if self.opt.cost == SROT_COST_F64 else torch.float32
+            out["dC"] = torch.empty(m, n, dtype=cdt, device=dev)
+        if dX:
+            out["dX"] = torch.empty(m, 3, dtype=torch.float32, device=dev)
+        if dY:
+            out["dY"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        if da:
+            out["da"] = torch.empty(m, dtype=torch.float64, device=dev)
+        if db:
+            out["db"] = torch.empty(n, dtype=torch.float64, device=dev)
+        srot_backward(self.h, grad_out, out.get("dC"), out.get("dX"), out.get("dY"),
+                      out.get("da"), out.get("db"))
+        return out
 
     def close(self):
         if self.h:

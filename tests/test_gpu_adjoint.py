@@ -1,0 +1,227 @@
+"""GPU adjoint (srot_backward, the autograd Function) against the oracle.
+
+* Parity at a given plan: the plan is loaded into the handle (srot_set_state)
+  and srot_backward's outputs are compared with oracle/adjoint.py's formulas
+  at the same plan.  dC (g t_ij rounded once to the cost dtype) must match
+  bit for bit; FP64 outputs (da, db) within 1e-13 relative to their largest
+  entry (the two sides round the residual's column sums in different
+  orders); FP32 point gradients within 1e-6 relative to their largest entry
+  (one FP32 rounding of an FP64 sum).
+* Finite differences: at a KKT-polished optimum (oracle) of the m = n = 64
+  fused problem, the GPU gradients agree with FP64 central differences of
+  the optimal value to relative error <= 1e-5.
+* End to end: after a GPU solve to gap G, db lies within sqrt(2 w G) of
+  -w r* (strong convexity of f in r; r* from polishing the GPU's plan).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as A
+from oracle import oracle as O
+from paper_2103_05857_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _S():
+    from paper_2103_05857_amd import srot as S
+    return S
+
+
+def _solver(d, cost_mode, w, **opts):
+    S = _S()
+    a = torch.from_numpy(d["a"]).to(DEV)
+    b = torch.from_numpy(d["b"]).to(DEV)
+    X = torch.from_numpy(d["X"]).to(DEV)
+    Y = torch.from_numpy(d["Y"]).to(DEV)
+    if cost_mode == "sqeuclid":
+        return S.Solver(a, b, X=X, Y=Y, w=w, **opts)
+    C = torch.from_numpy(d["C"]).to(DEV)
+    return S.Solver(a, b, C=C, X=X, Y=Y, w=w, **opts)
+
+
+def _cost64(d, cost_mode):
+    if cost_mode == "sqeuclid":
+        return A.sqeuclid_cost(d["X"], d["Y"])
+    return d["C"].astype(np.float64)
+
+
+def _oracle_plan(d, cost_mode, w, passes, seed=0):
+    m = d["a"].shape[0]
+    if cost_mode == "sqeuclid":
+        P = O.Problem(d["a"], d["b"], w, X=d["X"], Y=d["Y"])
+    else:
+        P = O.Problem(d["a"], d["b"], w, C=d["C"].astype(np.float64))
+    st, _ = O.solve(P, lambda p: I.philox_uniform_indices(seed, p * m, m, m),
+                    max_passes=passes, gap_every=passes)
+    return st.T
+
+
+def _rel(x, ref):
+    return float(np.max(np.abs(x - ref)) / max(float(np.max(np.abs(ref))), 1e-300))
+
+
+def _run_backward(sol, T, g, cost_mode):
+    sol.set_state(torch.from_numpy(T).to(DEV), 0)
+    out = sol.backward(g, dC=(cost_mode != "sqeuclid"), dX=True, dY=True, da=True, db=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w,passes", [
+    ("sqeuclid", np.float32, 64, 64, 1.0, 40),
+    ("sqeuclid", np.float32, 37, 1111, 0.3, 12),
+    ("stored", np.float32, 300, 700, 1.0, 6),
+    ("stored", np.float64, 200, 257, 10.0, 8),
+    ("sqeuclid", np.float32, 41, 5000, 1.0, 6),     # wide-row ownership
+    ("stored", np.float32, 33, 4100, 0.1, 6),       # wide-row ownership, stored
+])
+def test_backward_matches_oracle_adjoint_at_a_plan(cost_mode, dtype, m, n, w, passes):
+    d = I.problem_mixture(3, m, n, cost_dtype=dtype)
+    T = _oracle_plan(d, cost_mode, w, passes)
+    g = 1.7
+    sol = _solver(d, cost_mode, w)
+    got = _run_backward(sol, T, g, cost_mode)
+    ref = A.adjoint(_cost64(d, cost_mode), d["a"], d["b"], w, T, X=d["X"], Y=d["Y"], grad_out=g)
+    if cost_mode != "sqeuclid":
+        want = (g * T).astype(dtype)
+        assert got["dC"].dtype == dtype
+        assert np.array_equal(got["dC"], want)
+    assert _rel(got["db"], ref["db"]) <= 1e-13
+    assert _rel(got["da"], ref["da"]) <= 1e-13
+    assert _rel(got["dX"], ref["dX"]) <= 1e-6
+    assert _rel(got["dY"], ref["dY"]) <= 1e-6
+    # bit-reproducible
+    again = _run_backward(sol, T, g, cost_mode)
+    for k in got:
+        assert np.array_equal(got[k], again[k]), k
+    sol.close()
+
+
+@pytest.fixture(scope="module")
+def polished64():
+    d = I.problem_mixture(0, 64, 64, cost_dtype=np.float64)
+    C = A.sqeuclid_cost(d["X"], d["Y"])
+    P = O.Problem(d["a"], d["b"], 1.0, C=C)
+    st, _ = O.solve(P, lambda p: I.philox_uniform_indices(0, p * 64, 64, 64),
+                    max_passes=1500, gap_every=1500)
+    T, mu, _ = A.kkt_polish(C, d["a"], d["b"], 1.0, st.T)
+    return d, C, T
+
+
+def _value(C, a, b, w, T_guess):
+    T, _, _ = A.kkt_polish(C, a, b, w, T_guess)
+    return A.objective(C, b, w, T)
+
+
+def test_backward_matches_finite_differences_m64(polished64):
+    d, C, T = polished64
+    X = d["X"].astype(np.float64)
+    Y = d["Y"].astype(np.float64)
+    a, b, w = d["a"], d["b"], 1.0
+    sol = _solver(d, "sqeuclid", w)
+    got = _run_backward(sol, T, 1.0, "sqeuclid")
+    sol.close()
+    h = 1e-6
+    fdX = np.zeros_like(X)
+    for i in range(64):
+        for k in range(3):
+            Xp = X.copy(); Xp[i, k] += h
+            Xm = X.copy(); Xm[i, k] -= h
+            fdX[i, k] = (_value(A.sqeuclid_cost(Xp, Y), a, b, w, T)
+                         - _value(A.sqeuclid_cost(Xm, Y), a, b, w, T)) / (2 * h)
+    fdY = np.zeros_like(Y)
+    for j in range(64):
+        for k in range(3):
+            Yp = Y.copy(); Yp[j, k] += h
+            Ym = Y.copy(); Ym[j, k] -= h
+            fdY[j, k] = (_value(A.sqeuclid_cost(X, Yp), a, b, w, T)
+                         - _value(A.sqeuclid_cost(X, Ym), a, b, w, T)) / (2 * h)
+    fdb = np.zeros_like(b)
+    for j in range(64):
+        bp = b.copy(); bp[j] += h
+        bm = b.copy(); bm[j] -= h
+        fdb[j] = (_value(C, a, bp, w, T) - _value(C, a, bm, w, T)) / (2 * h)
+    fda = np.zeros_like(a)
+    for i in range(64):
+        ap = a.copy(); ap[i] += h
+        am = a.copy(); am[i] -= h
+        fda[i] = (_value(C, ap, b, w, T) - _value(C, am, b, w, T)) / (2 * h)
+    assert _rel(got["dX"], fdX) <= 1e-5
+    assert _rel(got["dY"], fdY) <= 1e-5
+    assert _rel(got["db"], fdb) <= 1e-5
+    assert _rel(got["da"], fda) <= 1e-5
+
+
+def test_end_to_end_db_within_the_gap_bound():
+    d = I.problem_mixture(1, 64, 64, cost_dtype=np.float64)
+    w = 1.0
+    sol = _solver(d, "sqeuclid", w, eps=1e-8, max_passes=5000)
+    status, (G, f, D), passes = sol.solve()
+    out = sol.backward(1.0, db=True)
+    T, _ = sol.plan()
+    torch.cuda.synchronize()
+    T = T.cpu().numpy()
+    db = out["db"].cpu().numpy()
+    C = A.sqeuclid_cost(d["X"], d["Y"])
+    Ts, _, _ = A.kkt_polish(C, d["a"], d["b"], w, T)
+    rstar = Ts.sum(axis=0) - d["b"]
+    assert G >= 0.0
+    assert np.linalg.norm(db - (-w * rstar)) <= np.sqrt(2 * w * G) * (1 + 1e-9) + 1e-15
+    sol.close()
+
+
+def test_autograd_function_fused_and_stored():
+    from paper_2103_05857_amd.autograd import semi_relaxed_ot
+    d = I.problem_mixture(2, 48, 80, cost_dtype=np.float32)
+    a = torch.from_numpy(d["a"]).to(DEV).requires_grad_(True)
+    b = torch.from_numpy(d["b"]).to(DEV).requires_grad_(True)
+    X = torch.from_numpy(d["X"]).to(DEV).requires_grad_(True)
+    Y = torch.from_numpy(d["Y"]).to(DEV).requires_grad_(True)
+    V = semi_relaxed_ot(a, b, X=X, Y=Y, w=1.0, eps=1e-8, max_passes=3000)
+    (2.0 * V).backward()
+    # same run through the plain solver: same plan (deterministic), then the oracle formulas
+    sol = _solver(d, "sqeuclid", 1.0, eps=1e-8, max_passes=3000)
+    _, (g, f, D), _ = sol.solve()
+    T, _ = sol.plan()
+    T = T.cpu().numpy()
+    sol.close()
+    assert abs(V.item() - f) == 0.0
+    ref = A.adjoint(A.sqeuclid_cost(d["X"], d["Y"]), d["a"], d["b"], 1.0, T,
+                    X=d["X"], Y=d["Y"], grad_out=2.0)
+    assert _rel(X.grad.cpu().numpy(), ref["dX"]) <= 1e-6
+    assert _rel(Y.grad.cpu().numpy(), ref["dY"]) <= 1e-6
+    assert _rel(a.grad.cpu().numpy(), ref["da"]) <= 1e-13
+    assert _rel(b.grad.cpu().numpy(), ref["db"]) <= 1e-13
+
+    C = torch.from_numpy(d["C"]).to(DEV).requires_grad_(True)
+    V2 = semi_relaxed_ot(a.detach(), b.detach(), C=C, w=1.0, eps=1e-8, max_passes=3000)
+    V2.backward()
+    assert C.grad.dtype == torch.float32
+    assert torch.all(C.grad >= 0)
+    np.testing.assert_allclose(C.grad.sum(dim=1).cpu().numpy(), d["a"], rtol=1e-6)
+
+
+def test_backward_error_paths():
+    S = _S()
+    d = I.problem_mixture(4, 16, 20, cost_dtype=np.float32)
+    a = torch.from_numpy(d["a"]).to(DEV)
+    b = torch.from_numpy(d["b"]).to(DEV)
+    C = torch.from_numpy(d["C"]).to(DEV)
+    X = torch.from_numpy(d["X"]).to(DEV)
+    Y = torch.from_numpy(d["Y"]).to(DEV)
+    stored = S.Solver(a, b, C=C)
+    with pytest.raises(S.SrotError) as e:
+        stored.backward(1.0, dX=True)           # no points given
+    assert e.value.status == S.SROT_EINVAL
+    with pytest.raises(S.SrotError):
+        stored.backward(float("nan"), db=True)
+    fused = S.Solver(a, b, X=X, Y=Y)
+    dC = torch.empty(16, 20, dtype=torch.float32, device=DEV)
+    with pytest.raises(S.SrotError):
+        S.srot_backward(fused.h, 1.0, dC=dC)    # the fused cost has no C
+    stored.close()
+    fused.close()
