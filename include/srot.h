@@ -180,6 +180,63 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
 int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *dY,
                   double *da, double *db);
 
+/* ------------------------------------------------------------------------
+ * Batched solver: many independent problems of uneven sizes, each solved
+ * from the initial plan to g <= eps (or max_passes) by Alg. 1 with the
+ * per-pass gap test of Sec. 3.1, all in one graph launch.  Every problem
+ * uses the options given (w, step rule, seed, eps, max_passes, gap_every);
+ * problem p follows the trajectory srot_solve would take on it alone with
+ * the same tile shape.  Stored FP32 cost and uniform sampling only; rows of
+ * at most 4096 columns.
+ * ------------------------------------------------------------------------ */
+typedef struct srot_batch srot_batch;   /* opaque */
+
+/* Bytes of device workspace for `count` problems of sizes m[p] x n[p]
+ * (host arrays); 0 for invalid sizes. */
+size_t srot_workspace_size_batched(int32_t count, const int64_t *m, const int64_t *n,
+                                   const srot_options *opt);
+
+/* Creates the batch.
+ *   m, n     host, count sizes (1 <= m[p] <= 2^31 - 1, 1 <= n[p] <= 4096).
+ *   c_off    host, count element offsets of each cost matrix in C, or NULL
+ *            for matrices stored back to back.  An offset that is a
+ *            multiple of 4 (with n[p] % 4 == 0) allows 16-byte cost loads.
+ *   C        device, float: problem p's m x n cost matrix at C + c_off[p].
+ *   a, b     device, doubles: the problems' weights back to back (problem
+ *            p's a at offset sum_{q<p} m[q], its b at sum_{q<p} n[q]).
+ *   workspace  device, >= srot_workspace_size_batched bytes, 256-byte aligned.
+ *   opt      host; cost must be SROT_COST_F32, sampling SROT_UNIFORM.
+ *   tune     0: each problem gets the tile shape srot_init would choose;
+ *            1: per group of problems sharing that shape, every compiled
+ *            candidate shape is timed on the group's largest problem (two
+ *            passes) and the fastest is kept.
+ *   stream   hipStream_t for all work of the batch.
+ * Validates the inputs on the device, builds and instantiates the graph,
+ * and synchronises.  Errors: SROT_EINVAL, SROT_ENOMEM, SROT_ENONFINITE,
+ * SROT_EHIP. */
+int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const int64_t *n,
+                      const int64_t *c_off, const float *C, const double *a, const double *b,
+                      void *workspace, size_t ws_bytes, const srot_options *opt, int32_t tune,
+                      void *stream);
+
+/* Solves every problem from its initial plan (one graph launch) and
+ * synchronises.  Host outputs, each optional: out3 (count x 3: g, f, D at
+ * the last gap sweep), passes (count), status (count: SROT_OK or
+ * SROT_NOT_CONVERGED).  Returns SROT_OK when every problem converged,
+ * SROT_NOT_CONVERGED otherwise. */
+int srot_solve_batched(srot_batch *h, double *out3, int64_t *passes, int32_t *status);
+
+/* Copies problem p's plan (device, m x n double, zeros off the support) and
+ * residual (device, n double); either may be NULL.  Enqueued on the stream. */
+int srot_get_plan_batched(srot_batch *h, int32_t p, double *T_out, double *r_out);
+
+/* Tile shape of every problem (host, count x 3: threads, columns per
+ * thread, vector width) and, when tuned, the measured milliseconds per
+ * block step of its group's shape (host, count floats, or NULL). */
+int srot_get_tiles_batched(srot_batch *h, int32_t *tiles, float *ms_per_step);
+
+void srot_destroy_batched(srot_batch *h);
+
 /* Destroys the handle (host memory only; the caller frees its buffers). */
 void srot_destroy(srot_handle *h);
 

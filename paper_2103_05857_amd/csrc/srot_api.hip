@@ -22,9 +22,10 @@ struct srot_handle {
 };
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
+namespace srot {
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -35,6 +36,10 @@ int fail(int code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
+}  // namespace srot
+
+namespace {
+using srot::fail;
 
 #define SROT_HIP(call)                                                                      \
     do {                                                                                    \

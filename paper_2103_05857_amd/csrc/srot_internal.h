@@ -54,6 +54,10 @@ struct DeviceState {
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
 };
 
+// Records a printf-style message as the calling thread's last error
+// (srot_last_error) and returns code.
+int fail(int code, const char *fmt, ...);
+
 // Ownership chosen for an n-column problem with the given cost storage;
 // aligned16: the cost matrix base is 16-byte aligned (honours
 // SROT_CHAIN_VARIANT).

@@ -77,6 +77,19 @@ def load():
     L.srot_set_state.restype = ctypes.c_int
     L.srot_backward.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
     L.srot_backward.restype = ctypes.c_int
+    L.srot_workspace_size_batched.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.POINTER(srot_options)]
+    L.srot_workspace_size_batched.restype = ctypes.c_size_t
+    L.srot_init_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    ctypes.c_size_t, ctypes.POINTER(srot_options), ctypes.c_int32, _vp]
+    L.srot_init_batched.restype = ctypes.c_int
+    L.srot_solve_batched.argtypes = [_vp, _vp, _vp, _vp]
+    L.srot_solve_batched.restype = ctypes.c_int
+    L.srot_get_plan_batched.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+    L.srot_get_plan_batched.restype = ctypes.c_int
+    L.srot_get_tiles_batched.argtypes = [_vp, _vp, _vp]
+    L.srot_get_tiles_batched.restype = ctypes.c_int
+    L.srot_destroy_batched.argtypes = [_vp]
+    L.srot_destroy_batched.restype = None
     L.srot_destroy.argtypes = [_vp]
     L.srot_destroy.restype = None
     L.srot_strerror.argtypes = [ctypes.c_int]
@@ -160,6 +173,111 @@ def srot_backward(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):
 def srot_destroy(h):
     if h:
         load().srot_destroy(h)
+
+
+def _host_ptr(arr):
+    return None if arr is None else ctypes.c_void_p(arr.ctypes.data)
+
+
+def srot_workspace_size_batched(m, n, opt):
+    import numpy as np
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    return int(load().srot_workspace_size_batched(len(m), _host_ptr(m), _host_ptr(n), ctypes.byref(opt)))
+
+
+def srot_init_batched(m, n, c_off, C, a, b, workspace, opt, tune=0):
+    import numpy as np
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    c_off = None if c_off is None else np.ascontiguousarray(c_off, dtype=np.int64)
+    h = ctypes.c_void_p()
+    _check(load().srot_init_batched(ctypes.byref(h), len(m), _host_ptr(m), _host_ptr(n), _host_ptr(c_off),
+                                    _ptr(C), _ptr(a), _ptr(b), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), ctypes.byref(opt),
+                                    int(tune), _stream()))
+    return h
+
+
+def srot_solve_batched(h, count):
+    import numpy as np
+    out3 = np.empty((count, 3), dtype=np.float64)
+    passes = np.empty(count, dtype=np.int64)
+    status = np.empty(count, dtype=np.int32)
+    st = _check(load().srot_solve_batched(h, _host_ptr(out3), _host_ptr(passes), _host_ptr(status)),
+                allow=(SROT_OK, SROT_NOT_CONVERGED))
+    return st, out3, passes, status
+
+
+def srot_get_plan_batched(h, p, T_out=None, r_out=None):
+    _check(load().srot_get_plan_batched(h, int(p), _ptr(T_out), _ptr(r_out)))
+
+
+def srot_get_tiles_batched(h, count):
+    import numpy as np
+    tiles = np.empty((count, 3), dtype=np.int32)
+    ms = np.empty(count, dtype=np.float32)
+    _check(load().srot_get_tiles_batched(h, _host_ptr(tiles), _host_ptr(ms)))
+    return tiles, ms
+
+
+def srot_destroy_batched(h):
+    if h:
+        load().srot_destroy_batched(h)
+
+
+class BatchSolver:
+    """Many independent problems with stored FP32 costs (srot_init_batched).
+
+    Cs: list of (m_p, n_p) float32 CUDA tensors; As, Bs: lists of float64 CUDA
+    tensors.  The costs are packed into one buffer with 16-byte aligned
+    offsets; the weights back to back."""
+
+    def __init__(self, Cs, As, Bs, tune=False, **options):
+        import numpy as np
+        options.setdefault("cost", SROT_COST_F32)
+        self.opt = srot_default_options(**options)
+        self.count = len(Cs)
+        self.m = np.array([c.shape[0] for c in Cs], dtype=np.int64)
+        self.n = np.array([c.shape[1] for c in Cs], dtype=np.int64)
+        dev = Cs[0].device
+        sizes = self.m * self.n
+        padded = (sizes + 3) // 4 * 4
+        self.c_off = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
+        self.C = torch.zeros(int(padded.sum()), dtype=torch.float32, device=dev)
+        for p, c in enumerate(Cs):
+            self.C[int(self.c_off[p]):int(self.c_off[p] + sizes[p])] = c.reshape(-1)
+        self.a = torch.cat([x.reshape(-1) for x in As]).to(torch.float64).contiguous()
+        self.b = torch.cat([x.reshape(-1) for x in Bs]).to(torch.float64).contiguous()
+        nbytes = srot_workspace_size_batched(self.m, self.n, self.opt)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.h = srot_init_batched(self.m, self.n, self.c_off, self.C, self.a, self.b, self.workspace,
+                                   self.opt, tune=1 if tune else 0)
+
+    def solve(self):
+        """(status, out3 (count x 3: g, f, D), passes, per-problem status)."""
+        return srot_solve_batched(self.h, self.count)
+
+    def plan(self, p):
+        dev = self.workspace.device
+        T = torch.empty(int(self.m[p]), int(self.n[p]), dtype=torch.float64, device=dev)
+        r = torch.empty(int(self.n[p]), dtype=torch.float64, device=dev)
+        srot_get_plan_batched(self.h, p, T, r)
+        return T, r
+
+    def tiles(self):
+        return srot_get_tiles_batched(self.h, self.count)
+
+    def close(self):
+        if self.h:
+            srot_destroy_batched(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Solver:
