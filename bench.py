@@ -58,6 +58,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solves")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--sections", type=str, default="batched,diff,fused",
+                    help="extra workloads after the stored-cost one: batched, diff, fused")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--seq-sample", type=int, default=64,
+                    help="problems of the batch solved one by one for the sequential baseline")
+    ap.add_argument("--fused-n", type=int, default=32768)
+    ap.add_argument("--fused-seconds", type=float, default=60.0,
+                    help="time cap of the fused-cost solve")
     return ap.parse_args()
 
 
@@ -168,7 +176,160 @@ def main():
         "time_to_gap_1e-6": ttg,
         "mean_row_nnz": nnz,
     }
+    sections = [x for x in args.sections.split(",") if x]
+    if "batched" in sections:
+        out["batched"] = bench_batched(args)
+    if "diff" in sections:
+        out["differentiation"] = bench_diff(args)
+    if "fused" in sections:
+        out["fused"] = bench_fused(args)
     print(json.dumps(out))
+
+
+def bench_batched(args):
+    """512 problems, m and n each log-uniform in [64, 4096], mixture palettes,
+    FP32 stored cost, uniform weights, w = 1, every problem to gap 1e-6: one
+    batched graph launch (autotuned tile shapes) against the single-problem
+    solver run on the problems one after another (a sample, extrapolated by
+    block updates)."""
+    import torch
+    from paper_2103_05857_amd import inputs as I
+    from paper_2103_05857_amd import srot as S
+    dev = torch.device("cuda:0")
+    count = args.batch_count
+    ms, ns = I.batched_sizes(0, count)
+    Cs, As, Bs = [], [], []
+    for p in range(count):
+        d = I.batched_problem(0, p, int(ms[p]), int(ns[p]))
+        X = torch.from_numpy(d["X"]).to(dev).double()
+        Y = torch.from_numpy(d["Y"]).to(dev).double()
+        Cs.append(((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1).float())
+        As.append(torch.from_numpy(d["a"]).to(dev))
+        Bs.append(torch.from_numpy(d["b"]).to(dev))
+    torch.cuda.synchronize()
+    opts = dict(w=1.0, eps=1e-6, max_passes=20000, seed=0)
+    t0 = time.perf_counter()
+    bs = S.BatchSolver(Cs, As, Bs, tune=True, **opts)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    bs.solve()                                   # warm-up replay
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        st, out3, passes, status = bs.solve()
+        times.append(time.perf_counter() - t0)
+    tiles, _ = bs.tiles()
+    bs.close()
+    solve_s = float(np.median(times))
+    updates = int((passes * ms).sum())
+    # cost bytes streamed: a row of 4n bytes per block step, 4mn per gap sweep
+    cbytes = float((passes * ms * 4 * ns).sum() + (passes * 4 * ms * ns).sum())
+    seq_s, seq_updates = 0.0, 0
+    k = min(args.seq_sample, count)
+    for p in range(k):
+        sol = S.Solver(As[p], Bs[p], C=Cs[p], **opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, np1 = sol.solve()
+        seq_s += time.perf_counter() - t0
+        seq_updates += np1 * int(ms[p])
+        sol.close()
+    seq_rate = seq_updates / seq_s
+    uniq, cnt = np.unique(tiles, axis=0, return_counts=True)
+    return {
+        "workload": f"{count} problems, m,n log-uniform in [64,4096], FP32 stored cost, w=1, gap<=1e-6",
+        "converged": int((status == 0).sum()), "seconds": solve_s,
+        "block_updates": updates, "block_updates_per_s": updates / solve_s,
+        "c_stream_GBps": cbytes / solve_s / 1e9, "c_stream_frac_hbm": cbytes / solve_s / 1e9 / HBM_PEAK_GBS,
+        "passes_mean": float(passes.mean()), "passes_max": int(passes.max()),
+        "init_and_autotune_s": init_s,
+        "tiles": {f"{a}x{b}x{c}": int(n_) for (a, b, c), n_ in zip(uniq.tolist(), cnt.tolist())},
+        "sequential": {"sample_problems": k, "seconds": seq_s, "block_updates_per_s": seq_rate,
+                       "extrapolated_seconds_all": updates / seq_rate},
+        "speedup_vs_sequential": (updates / seq_rate) / solve_s,
+    }
+
+
+def bench_diff(args):
+    """Differentiation: m = n = 4096 mixture points (fused squared-Euclidean
+    cost), w = 1, V = optimal value solved to gap 1e-6; forward alone against
+    forward plus backward (dX, dY, da, db through srot_backward)."""
+    import torch
+    from paper_2103_05857_amd import inputs as I
+    from paper_2103_05857_amd.autograd import semi_relaxed_ot
+    dev = torch.device("cuda:0")
+    d = I.problem_mixture(0, 4096, 4096, with_cost=False)
+    X0 = torch.from_numpy(d["X"]).to(dev)
+    Y0 = torch.from_numpy(d["Y"]).to(dev)
+    a0 = torch.from_numpy(d["a"]).to(dev)
+    b0 = torch.from_numpy(d["b"]).to(dev)
+    fwd, both = [], []
+    for rep in range(3):
+        X = X0.clone().requires_grad_(True)
+        Y = Y0.clone().requires_grad_(True)
+        a = a0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V = semi_relaxed_ot(a, b, X=X, Y=Y, w=1.0, eps=1e-6, max_passes=5000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        V.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd.append(t1 - t0)
+        both.append(t2 - t0)
+    return {"workload": "m=n=4096 mixture points, fused cost, w=1, V solved to gap 1e-6",
+            "forward_s": float(np.median(fwd)), "forward_backward_s": float(np.median(both)),
+            "backward_s": float(np.median(np.array(both) - np.array(fwd)))}
+
+
+def bench_fused(args):
+    """Fused on-the-fly cost: m = n = 32768 mixture points (the cost, 4 GiB in
+    FP32, is never stored), a uniform, b ~ Dirichlet(1), w = 1, run to gap
+    1e-5 or the time cap."""
+    import torch
+    from paper_2103_05857_amd import inputs as I
+    from paper_2103_05857_amd import srot as S
+    dev = torch.device("cuda:0")
+    n = args.fused_n
+    d = I.problem_mixture(0, n, n, dirichlet_b=True, with_cost=False)
+    X = torch.from_numpy(d["X"]).to(dev)
+    Y = torch.from_numpy(d["Y"]).to(dev)
+    a = torch.from_numpy(d["a"]).to(dev)
+    b = torch.from_numpy(d["b"]).to(dev)
+    sol = S.Solver(a, b, X=X, Y=Y, w=1.0, seed=0, eps=1e-5)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    hist = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    step_ms, gap_ms = [], []
+    t0 = time.perf_counter()
+    g = float("inf")
+    passes = 0
+    while time.perf_counter() - t0 < args.fused_seconds:
+        e0.record(stream)
+        S.srot_step(sol.h, n)
+        e1.record(stream)
+        g, f, D = S.srot_gap(sol.h)
+        step_ms.append(e0.elapsed_time(e1))
+        passes += 1
+        hist.append((passes, g))
+        if g <= 1e-5:
+            break
+    wall = time.perf_counter() - t0
+    sol.close()
+    us_step = 1000.0 * float(np.median(step_ms)) / n
+    # per block step: n cost evaluations (3 sub, 3 FMA-class ops) plus the
+    # gradient entry and compare, about 10 FP64 flops each
+    flops_step = 10.0 * n
+    return {"workload": f"m=n={n} mixture points, fused squared-Euclidean cost, b~Dirichlet(1), w=1, "
+                        f"to gap 1e-5 (cap {args.fused_seconds:.0f} s)",
+            "passes": passes, "gap": g, "converged": bool(g <= 1e-5), "seconds": wall,
+            "us_per_block_update": us_step, "block_updates_per_s": 1e6 / us_step,
+            "fp64_GFLOPs_chain": flops_step / us_step / 1e3,
+            "gap_history": hist[:: max(1, len(hist) // 10)]}
 
 
 def cpu_baseline(d, m, w, seconds):

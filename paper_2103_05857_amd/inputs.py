@@ -107,3 +107,16 @@ def problem_mixture(seed: int, m: int, n: int, cost_dtype=np.float32, dirichlet_
     if with_cost:
         d["C"] = sqeuclid_cost(X, Y, cost_dtype)
     return d
+
+
+def batched_sizes(seed: int, count: int, lo: int = 64, hi: int = 4096):
+    """count (m, n) pairs, each side log-uniform in [lo, hi], rounded."""
+    rng = np.random.default_rng(seed)
+    ms = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)
+    ns = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)
+    return ms, ns
+
+
+def batched_problem(seed: int, p: int, m: int, n: int, with_cost: bool = False):
+    """Problem p of a batch: two mixture palettes, uniform weights."""
+    return problem_mixture(seed * 1000003 + 7 * p, m, n, cost_dtype=np.float32, with_cost=with_cost)
