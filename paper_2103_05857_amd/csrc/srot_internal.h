@@ -49,7 +49,7 @@ struct DeviceState {
     double *partials;      // gap_blocks x 4
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
-    int32_t *flags;        // 8: [0] validation/index error flag
+    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket
     int64_t *resume;       // step at which the prefetching chain kernel stopped
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
 };

@@ -21,15 +21,16 @@
 //                     in advance.  A step is two workgroup reductions: the
 //                     LMO argmin, then the line-search sums over the support.
 //   chain_glb_kernel  same step for wider rows: r in global memory (L2).
-//   gap_kernel        per-pass duality-gap sweep (Thm 2), one workgroup per
-//                     row at a time, streaming the cost row once: HBM bound.
-//   gap_final_kernel  deterministic fixed-order reduction of the sweep.
+//   gap_sweep_kernel  per-pass duality-gap sweep (Thm 2): each wave streams
+//                     whole cost rows (HBM bound); the last workgroup adds
+//                     the partials in a fixed order.
 //   sample kernels    counter-based Philox4x64-10 block indices.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <algorithm>
 #include <type_traits>
 
 #include "../../include/srot.h"
@@ -161,163 +162,276 @@ __global__ __launch_bounds__(GLB_NT) void chain_glb_kernel(ProblemView P, double
 }
 
 // ---------------------------------------------------------------------------
-// Gap sweep (Thm 2, eq. AppenEq:Gi, dual of App. D).  One workgroup handles
-// one row at a time with the handle's column ownership:
-//   G_i = min_j v_ij (lowest argmin j*_i),  g_i = sum_j t_ij (v_ij - G_i),
-//   lin_i = sum_j t_ij c_ij   (sums over the support only).
-// Thread 0 accumulates a_i G_i, lin_i and g_i over its rows in row order;
-// gap_final_kernel adds the workgroups in order.
-// CPT > 0: r held in registers (n <= NT * CPT); CPT == 0: r read from memory
-// (VEC must be 1 then).
+// Gap sweep (Thm 2, eq. AppenEq:Gi, dual of App. D), streaming the cost once.
+// A wave takes R rows at a time (row groups strided over the grid), with no
+// workgroup barrier per row:
+//   G_i = min_j v_ij, v_ij = c_ij + w r_j (lowest argmin j*_i),
+//   g_i = sum_j t_ij (v_ij - G_i),  lin_i = sum_j t_ij c_ij  (support only).
+// Lane l meets columns j = (q * 64 + l) * VEC + e in increasing order, so '<'
+// keeps the lowest index; 16 columns per lane are requested at once for each
+// of the R rows, and each r_j (read through L2, vectorised) serves the R
+// rows.  Per-row outputs go to row_G / row_j / row_g.  Row sums are added in
+// row order within a wave and waves in order within a workgroup; the last
+// workgroup to finish (ticket counter, reset by that workgroup) adds the
+// workgroup partials in a fixed tree order and writes
+//   out[0] = g = sum g_i,  out[1] = f = <T,C> + (w/2)||r||^2,
+//   out[2] = D = sum a_i G_i - w <b, r> - (w/2)||r||^2,  out[3] = <T,C>,
+//   out[4] = ||r||^2
+// (sum_i <t_i, grad_i f> = <T,C> + w <r + b, r> gives D = f - g).
 // ---------------------------------------------------------------------------
-template <int NT, int CPT, int VEC, int COST>
-__global__ __launch_bounds__(NT) void gap_kernel(ProblemView P, const double *__restrict__ T,
-                                                 const double *__restrict__ rg,
-                                                 const uint32_t *__restrict__ M, int words,
-                                                 double *__restrict__ row_G,
-                                                 int32_t *__restrict__ row_j,
-                                                 double *__restrict__ row_g,
-                                                 double *__restrict__ partials)
+constexpr int GAP_NT = 256;
+constexpr int GAP_NW = GAP_NT / 64;
+constexpr int GAP_MAX_BLOCKS = 1024;
+constexpr int GAP_KS = 2;  // support entries per lane and row gathered ahead of the scan
+
+template <int COST, int VEC, int R>
+__global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const double *__restrict__ T,
+                                                           const double *__restrict__ rg,
+                                                           const uint32_t *__restrict__ M, Ownership own,
+                                                           double *__restrict__ row_G,
+                                                           int32_t *__restrict__ row_j,
+                                                           double *__restrict__ row_g,
+                                                           double *__restrict__ partials,
+                                                           int32_t *__restrict__ ticket,
+                                                           double *__restrict__ out)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
-    constexpr int NW = NT / 64;
-    constexpr int RC = CPT > 0 ? CPT : 1;
-    __shared__ double s_v[2][NW];
-    __shared__ int s_j[2][NW];
-    __shared__ double s_sum[2][NW][2];
-    const int tid = threadIdx.x;
-    const int n = P.n, m = P.m;
+    constexpr int GU = 16 / VEC;  // vectors per lane per group: 16 columns
+    __shared__ double s_w[GAP_NW][3];
+    __shared__ double s_red[GAP_NW * 5];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int m = P.m, n = P.n;
     const double w = P.w;
     const CT *__restrict__ C = (const CT *)P.C;
+    const int slots = own.words * own.nt;
+    const int nq = (n + 64 * VEC - 1) / (64 * VEC);
 
-    double r[RC];
-    if constexpr (CPT > 0) {
+    double aG = 0.0, lin = 0.0, gs = 0.0;
+    const int stride = gridDim.x * GAP_NW * R;
+    for (int i0 = (blockIdx.x * GAP_NW + wid) * R; i0 < m; i0 += stride) {
+        int ir[R];
+        float xr[R][3];
 #pragma unroll
-        for (int u = 0; u < CPT; ++u) {
-            const int j = owned_col<NT, VEC>(u, tid);
-            r[u] = (j < n) ? rg[j] : 0.0;
-        }
-    }
-    auto cost = [&](int i, int j, float x0, float x1, float x2) -> double {
-        if constexpr (FUSED) return sqdist(x0, x1, x2, P.Y[3 * j], P.Y[3 * j + 1], P.Y[3 * j + 2]);
-        else return (double)C[(size_t)i * (size_t)n + j];
-    };
-
-    double acc_aG = 0.0, acc_lin = 0.0, acc_g = 0.0;
-    int par = 0;
-    for (int i = blockIdx.x; i < m; i += gridDim.x, par ^= 1) {
-        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-        if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
-        double best = INFINITY;
-        int bj = 0x7fffffff;
-        if constexpr (CPT > 0) {
-            CT cv[RC];
-            if constexpr (!FUSED) load_cost_row<NT, CPT, VEC, CT>(C + (size_t)i * (size_t)n, n, tid, cv);
-#pragma unroll
-            for (int u = 0; u < CPT; ++u) {
-                const int j = owned_col<NT, VEC>(u, tid);
-                double c;
-                if constexpr (FUSED) c = (j < n) ? cost(i, j, x0, x1, x2) : 0.0;
-                else c = (double)cv[u];
-                const double v = (j < n) ? c + w * r[u] : INFINITY;
-                if (v < best) { best = v; bj = j; }
-            }
-        } else {
-            for (int j = tid; j < n; j += NT) {
-                const double v = cost(i, j, x0, x1, x2) + w * rg[j];
-                if (v < best) { best = v; bj = j; }
+        for (int k = 0; k < R; ++k) {
+            ir[k] = (i0 + k < m) ? i0 + k : m - 1;
+            if constexpr (FUSED) {
+                xr[k][0] = P.X[3 * ir[k]]; xr[k][1] = P.X[3 * ir[k] + 1]; xr[k][2] = P.X[3 * ir[k] + 2];
             }
         }
-        block_argmin<NW>(best, bj, s_v[par], s_j[par]);
-        const double G = best;
-
-        double acc[2] = {0.0, 0.0};  // g_i, lin_i
-        const uint32_t *Mi = M + (size_t)i * words * NT + tid;
-        const size_t base = (size_t)i * (size_t)n;
-        for (int wd = 0; wd < words; ++wd) {
-            uint32_t mk = Mi[(size_t)wd * NT];
-            while (mk) {
-                const int b = __ffs(mk) - 1;
-                mk &= mk - 1u;
-                const int u = wd * 32 + b;
-                int j;
-                double rj;
-                if constexpr (CPT > 0) {
-                    j = owned_col<NT, VEC>(u, tid);
-                    rj = 0.0;
+        // The first GAP_KS support entries of each row in this lane's mask
+        // slots are requested before the cost rows, so their gathers overlap
+        // the stream; further entries (rare) are read after the scan.
+        int sj[R][GAP_KS];
+        double st[R][GAP_KS], sc[R][GAP_KS], sr[R][GAP_KS];
+        bool more[R];
 #pragma unroll
-                    for (int q = 0; q < CPT; ++q) rj = (q == u) ? r[q] : rj;
-                } else {
-                    j = u * NT + tid;
-                    rj = rg[j];
+        for (int k = 0; k < R; ++k) {
+            more[k] = false;
+            int found = 0;
+#pragma unroll
+            for (int e = 0; e < GAP_KS; ++e) sj[k][e] = -1;
+            if (i0 + k < m) {
+                for (int s = lane; s < slots; s += 64) {
+                    uint32_t mk = M[(size_t)ir[k] * slots + s];
+                    const int wd = s / own.nt, ts = s - wd * own.nt;
+                    while (mk) {
+                        const int b = __ffs(mk) - 1;
+                        mk &= mk - 1u;
+                        const int u = wd * 32 + b;
+                        const int j = ((u / own.vec) * own.nt + ts) * own.vec + (u % own.vec);
+                        if (found < GAP_KS) {
+#pragma unroll
+                            for (int e = 0; e < GAP_KS; ++e) sj[k][e] = (e == found) ? j : sj[k][e];
+                            ++found;
+                        } else {
+                            more[k] = true;
+                        }
+                    }
                 }
-                const double t = T[base + j];
-                const double c = cost(i, j, x0, x1, x2);
-                acc[0] += t * (c + w * rj - G);
-                acc[1] += t * c;
+            }
+#pragma unroll
+            for (int e = 0; e < GAP_KS; ++e) {
+                const int j = sj[k][e] >= 0 ? sj[k][e] : 0;
+                st[k][e] = T[(size_t)ir[k] * (size_t)n + j];
+                sr[k][e] = rg[j];
+                if constexpr (FUSED) {
+                    const float4 yj = P.Y4[j];
+                    sc[k][e] = sqdist(xr[k][0], xr[k][1], xr[k][2], yj.x, yj.y, yj.z);
+                } else {
+                    sc[k][e] = (double)C[(size_t)ir[k] * (size_t)n + j];
+                }
             }
         }
-        block_sum<NW, 2>(acc, s_sum[par]);
-        if (tid == 0) {
-            row_G[i] = G;
-            row_j[i] = bj;
-            row_g[i] = acc[0];
-            acc_aG += P.a[i] * G;
-            acc_lin += acc[1];
-            acc_g += acc[0];
+        double best[R];
+        int bj[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) { best[k] = INFINITY; bj[k] = 0x7fffffff; }
+        for (int q0 = 0; q0 < nq; q0 += GU) {
+            CT cv[R][GU][VEC];
+            if constexpr (!FUSED) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const CT *__restrict__ crow = C + (size_t)ir[k] * (size_t)n;
+#pragma unroll
+                    for (int u = 0; u < GU; ++u) {
+                        const int jb = ((q0 + u) * 64 + lane) * VEC;
+                        const int jc = jb < n ? jb : 0;
+                        if constexpr (VEC == 4) {
+                            const float4 v = *reinterpret_cast<const float4 *>(crow + jc);
+                            cv[k][u][0] = v.x; cv[k][u][1] = v.y; cv[k][u][2] = v.z; cv[k][u][3] = v.w;
+                        } else if constexpr (VEC == 2) {
+                            const double2 v = *reinterpret_cast<const double2 *>(crow + jc);
+                            cv[k][u][0] = v.x; cv[k][u][1] = v.y;
+                        } else {
+                            cv[k][u][0] = crow[jc];
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int jb = ((q0 + u) * 64 + lane) * VEC;
+                if (jb >= n) continue;
+                double rv[VEC];
+                if constexpr (VEC == 4) {
+                    const double2 ra = *reinterpret_cast<const double2 *>(rg + jb);
+                    const double2 rb = *reinterpret_cast<const double2 *>(rg + jb + 2);
+                    rv[0] = ra.x; rv[1] = ra.y; rv[2] = rb.x; rv[3] = rb.y;
+                } else if constexpr (VEC == 2) {
+                    const double2 ra = *reinterpret_cast<const double2 *>(rg + jb);
+                    rv[0] = ra.x; rv[1] = ra.y;
+                } else {
+                    rv[0] = rg[jb];
+                }
+                float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+                if constexpr (FUSED) y = P.Y4[jb];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        double c;
+                        if constexpr (FUSED) c = sqdist(xr[k][0], xr[k][1], xr[k][2], y.x, y.y, y.z);
+                        else c = (double)cv[k][u][e];
+                        const double v = c + w * rv[e];
+                        if (v < best[k]) { best[k] = v; bj[k] = jb + e; }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (i0 + k >= m) break;  // uniform over the wave
+            const int i = i0 + k;
+            double G = best[k];
+            int J = bj[k];
+            wave_argmin(G, J);
+            double x[2] = {0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < GAP_KS; ++e) {
+                if (sj[k][e] >= 0) {
+                    x[0] += st[k][e] * (sc[k][e] + w * sr[k][e] - G);
+                    x[1] += st[k][e] * sc[k][e];
+                }
+            }
+            if (__any(more[k])) {
+                int seen = 0;  // entries of this lane already added
+                for (int s = lane; s < slots; s += 64) {
+                    const int wd = s / own.nt, ts = s - wd * own.nt;
+                    uint32_t mk = more[k] ? M[(size_t)i * slots + s] : 0u;
+                    while (mk) {
+                        const int b = __ffs(mk) - 1;
+                        mk &= mk - 1u;
+                        if (seen++ < GAP_KS) continue;
+                        const int u = wd * 32 + b;
+                        const int j = ((u / own.vec) * own.nt + ts) * own.vec + (u % own.vec);
+                        const double t = T[(size_t)i * (size_t)n + j];
+                        double c;
+                        if constexpr (FUSED) {
+                            const float4 yj = P.Y4[j];
+                            c = sqdist(xr[k][0], xr[k][1], xr[k][2], yj.x, yj.y, yj.z);
+                        } else {
+                            c = (double)C[(size_t)i * (size_t)n + j];
+                        }
+                        x[0] += t * (c + w * rg[j] - G);
+                        x[1] += t * c;
+                    }
+                }
+            }
+            wave_sum<2>(x);
+            if (lane == 0) {
+                row_G[i] = G;
+                row_j[i] = J;
+                row_g[i] = x[0];
+            }
+            aG += P.a[i] * G;
+            lin += x[1];
+            gs += x[0];
         }
     }
+    if (lane == 0) { s_w[wid][0] = aG; s_w[wid][1] = lin; s_w[wid][2] = gs; }
+    __syncthreads();
+    // Partials travel through device-scope atomics, which are performed at the
+    // coherent level; no cache write-back is needed.  The ticket increment
+    // takes an operand computed from the values the exchanges return, so it
+    // is issued only after every partial has landed.
     if (tid == 0) {
-        partials[4 * blockIdx.x + 0] = acc_aG;
-        partials[4 * blockIdx.x + 1] = acc_lin;
-        partials[4 * blockIdx.x + 2] = acc_g;
+        double t3[3] = {s_w[0][0], s_w[0][1], s_w[0][2]};
+#pragma unroll
+        for (int k = 1; k < GAP_NW; ++k) { t3[0] += s_w[k][0]; t3[1] += s_w[k][1]; t3[2] += s_w[k][2]; }
+        unsigned long long seen = 0ull;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            seen ^= __hip_atomic_exchange(reinterpret_cast<unsigned long long *>(partials) + 4 * blockIdx.x + k,
+                                          (unsigned long long)__double_as_longlong(t3[k]), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        int zero;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(zero) : "v"((unsigned)(seen ^ (seen >> 32))));
+        const int got = __hip_atomic_fetch_add(ticket, 1 + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (got == (int)gridDim.x - 1);
     }
-}
-
-// Fixed-order tree reduction of a per-thread value over a 256-thread block.
-__device__ double block_sum_256(double v, double *sh)
-{
-    sh[threadIdx.x] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
+    if (!s_last) return;
+    auto part = [&](int k, int c) -> double {
+        return __longlong_as_double((long long)__hip_atomic_load(
+            reinterpret_cast<unsigned long long *>(partials) + 4 * k + c, __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT));
+    };
+    // fixed order: each thread's strided terms in index order, then the wave
+    // (DPP), then the four waves in order
+    double f5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // a_i G_i, lin, g, ||r||^2, <b, r>
+    for (int k = tid; k < (int)gridDim.x; k += GAP_NT) {
+        f5[0] += part(k, 0);
+        f5[1] += part(k, 1);
+        f5[2] += part(k, 2);
     }
-    const double out = sh[0];
+    for (int j = tid; j < n; j += GAP_NT) {
+        const double rj = rg[j];
+        f5[3] += rj * rj;
+        f5[4] += P.b[j] * rj;
+    }
+    wave_sum<5>(f5);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s_red[wid * 5 + c] = f5[c];
+    }
     __syncthreads();
-    return out;
-}
-
-// g = sum g_i;  f = <T,C> + (w/2)||r||^2;
-// D = sum a_i G_i - w <b, r> - (w/2)||r||^2   (App. D dual with
-//     sum_i <t_i, grad_i f> = <T,C> + w <r + b, r>).
-__global__ __launch_bounds__(256) void gap_final_kernel(ProblemView P, const double *__restrict__ rg,
-                                                        const double *__restrict__ partials,
-                                                        int nparts, double *__restrict__ out)
-{
-    __shared__ double sh[256];
-    double aG = 0.0, lin = 0.0, g = 0.0, rr = 0.0, br = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += 256) {
-        aG += partials[4 * k + 0];
-        lin += partials[4 * k + 1];
-        g += partials[4 * k + 2];
-    }
-    for (int j = threadIdx.x; j < P.n; j += 256) {
-        rr += rg[j] * rg[j];
-        br += P.b[j] * rg[j];
-    }
-    aG = block_sum_256(aG, sh);
-    lin = block_sum_256(lin, sh);
-    g = block_sum_256(g, sh);
-    rr = block_sum_256(rr, sh);
-    br = block_sum_256(br, sh);
-    if (threadIdx.x == 0) {
-        out[0] = g;
-        out[1] = lin + 0.5 * P.w * rr;
-        out[2] = aG - P.w * br - 0.5 * P.w * rr;
-        out[3] = lin;
+    if (tid == 0) {
+        double t5[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            t5[c] = s_red[c];
+#pragma unroll
+            for (int q = 1; q < GAP_NW; ++q) t5[c] += s_red[q * 5 + c];
+        }
+        const double pa = t5[0], pl = t5[1], pg = t5[2], rr = t5[3], br = t5[4];
+        out[0] = pg;
+        out[1] = pl + 0.5 * w * rr;
+        out[2] = pa - w * br - 0.5 * w * rr;
+        out[3] = pl;
         out[4] = rr;
+        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -628,47 +742,44 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
 
 int32_t gap_blocks_for(int64_t m)
 {
-    int64_t b = m;
+    int64_t b = (m + GAP_NW - 1) / GAP_NW;
     if (b < 1) b = 1;
-    if (b > 2048) b = 2048;
+    if (b > GAP_MAX_BLOCKS) b = GAP_MAX_BLOCKS;
     return (int32_t)b;
 }
 
-template <int COST>
-static hipError_t launch_gap_cost(const ProblemView &P, const DeviceState &S, hipStream_t st)
+template <int COST, int VEC, int R>
+static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, hipStream_t st)
 {
-    const Ownership &o = S.own;
-    const int nb = S.gap_blocks;
-    if (o.reg) {
-#define SROT_GAP(NT_, CPT_, VEC_)                                                                  \
-        if (o.nt == NT_ && o.cpt == CPT_ && o.vec == VEC_) {                                       \
-            hipLaunchKernelGGL((gap_kernel<NT_, CPT_, VEC_, COST>), dim3(nb), dim3(NT_), 0, st, P,   \
-                               S.T, S.r, S.mask, o.words, S.row_G, S.row_j, S.row_g, S.partials);  \
-            return hipGetLastError();                                                              \
-        }
-        SROT_VARIANTS_V1(SROT_GAP)
-        if constexpr (COST == SROT_COST_F32) { SROT_VARIANTS_V4(SROT_GAP) }
-        if constexpr (COST == SROT_COST_F64) { SROT_VARIANTS_V2(SROT_GAP) }
-#undef SROT_GAP
-        return hipErrorInvalidConfiguration;
-    }
-    hipLaunchKernelGGL((gap_kernel<GLB_NT, 0, 1, COST>), dim3(nb), dim3(GLB_NT), 0, st, P, S.T, S.r,
-                       S.mask, o.words, S.row_G, S.row_j, S.row_g, S.partials);
+    const int64_t waves = (P.m + R - 1) / R;
+    const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, GAP_MAX_BLOCKS),
+                                          S.gap_blocks);
+    hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
+                       S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars);
     return hipGetLastError();
+}
+
+// Two rows per wave: each r_j read serves both; more rows per wave would
+// cost occupancy (registers) for little further saving.
+template <int COST, int VEC>
+static hipError_t launch_gap_vec(const ProblemView &P, const DeviceState &S, hipStream_t st)
+{
+    return launch_gap_rows<COST, VEC, 2>(P, S, st);
 }
 
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream)
 {
-    hipError_t e;
+    const uintptr_t cbase = (uintptr_t)P.C;
     switch (P.cost) {
-    case SROT_COST_F32: e = launch_gap_cost<SROT_COST_F32>(P, S, stream); break;
-    case SROT_COST_F64: e = launch_gap_cost<SROT_COST_F64>(P, S, stream); break;
-    default: e = launch_gap_cost<SROT_COST_SQEUCLID>(P, S, stream); break;
+    case SROT_COST_F32:
+        if (P.n % 4 == 0 && cbase % 16 == 0) return launch_gap_vec<SROT_COST_F32, 4>(P, S, stream);
+        return launch_gap_vec<SROT_COST_F32, 1>(P, S, stream);
+    case SROT_COST_F64:
+        if (P.n % 2 == 0 && cbase % 16 == 0) return launch_gap_vec<SROT_COST_F64, 2>(P, S, stream);
+        return launch_gap_vec<SROT_COST_F64, 1>(P, S, stream);
+    default:
+        return launch_gap_vec<SROT_COST_SQEUCLID, 1>(P, S, stream);
     }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(256), 0, stream, P, S.r, S.partials,
-                       S.gap_blocks, S.scalars);
-    return hipGetLastError();
 }
 
 }  // namespace srot
