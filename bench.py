@@ -58,8 +58,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solves")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--sections", type=str, default="batched,diff,fused",
-                    help="extra workloads after the stored-cost one: batched, diff, fused")
+    ap.add_argument("--sections", type=str, default="sweep,batched,diff,fused",
+                    help="extra workloads after the stored-cost one: sweep, batched, diff, fused")
+    ap.add_argument("--sweep-n", type=int, default=16384)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=64,
                     help="problems of the batch solved one by one for the sequential baseline")
@@ -104,13 +105,16 @@ def main():
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
         evg = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        out5 = torch.empty(5, dtype=torch.float64, device=dev)
         t0 = time.perf_counter()
         for p in range(args.steps):
             ev[p][0].record(stream)
             S.srot_step(sol.h, m)            # one pass of m block updates
             ev[p][1].record(stream)
-            S.srot_gap(sol.h)                # gap sweep + stop-test readback (syncs)
+            S.srot_gap_async(sol.h, out5)    # gap sweep
             evg[p].record(stream)
+            evg[p].synchronize()
+            _ = out5[0].item()               # stop-test readback
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         total_updates += args.steps * m
@@ -150,11 +154,11 @@ def main():
     gap_avg_ms = float(np.median(gap_ms))
     gap_bytes = 4.0 * m * n + 12.0 * nnz * m + 8.0 * (3 * m + n)
     gap_achieved = gap_bytes / (gap_avg_ms * 1e-3) / 1e9
-    gap_sweep = dict(kernel="gap_kernel<256,16,4,f32> + gap_final_kernel", bound="hbm",
+    gap_sweep = dict(kernel="gap_sweep_kernel<f32,4,2>", bound="hbm",
                      achieved=gap_achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                      frac=gap_achieved / HBM_PEAK_GBS, bytes_per_launch=gap_bytes,
-                     launch_ms_incl_readback=gap_avg_ms,
-                     traffic=counter_traffic("srot::gap_kernel<256, 16, 4, 0>"))
+                     launch_ms=gap_avg_ms,
+                     traffic=counter_traffic("srot::gap_sweep_kernel<0, 4, 2>"))
 
     cpu = None
     if not args.no_cpu:
@@ -177,6 +181,8 @@ def main():
         "mean_row_nnz": nnz,
     }
     sections = [x for x in args.sections.split(",") if x]
+    if "sweep" in sections:
+        out["gap_sweep_1GiB"] = bench_sweep(args)
     if "batched" in sections:
         out["batched"] = bench_batched(args)
     if "diff" in sections:
@@ -184,6 +190,55 @@ def main():
     if "fused" in sections:
         out["fused"] = bench_fused(args)
     print(json.dumps(out))
+
+
+def bench_sweep(args):
+    """The per-pass gap sweep on a cost larger than the 256 MB Infinity Cache:
+    m = n = 16384 mixture points, FP32 stored cost (1 GiB), after one pass of
+    block steps from the initial plan; kernel time from HIP events around
+    srot_gap_async on the solver's stream."""
+    import torch
+    from paper_2103_05857_amd import inputs as I
+    from paper_2103_05857_amd import srot as S
+    dev = torch.device("cuda:0")
+    n = args.sweep_n
+    d = I.problem_mixture(0, n, n, with_cost=False)
+    X = torch.from_numpy(d["X"]).to(dev).double()
+    Y = torch.from_numpy(d["Y"]).to(dev).double()
+    C = torch.empty(n, n, dtype=torch.float32, device=dev)
+    for i0 in range(0, n, 2048):
+        C[i0:i0 + 2048] = ((X[i0:i0 + 2048, None, :] - Y[None, :, :]) ** 2).sum(-1).float()
+    del X, Y
+    a = torch.from_numpy(d["a"]).to(dev)
+    b = torch.from_numpy(d["b"]).to(dev)
+    sol = S.Solver(a, b, C=C, w=1.0, seed=0)
+    S.srot_step(sol.h, n)
+    out5 = torch.empty(5, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        S.srot_gap_async(sol.h, out5)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(10):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.srot_gap_async(sol.h, out5)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    T, _ = sol.plan()
+    nnz = int((T > 0).sum().item())
+    del T
+    sol.close()
+    t = float(np.median(ms)) * 1e-3
+    # algorithmic bytes: the cost once (4 m n), the plan's support (index +
+    # value, 12 B per nonzero), r, b, a and the per-row outputs
+    byts = 4.0 * n * n + 12.0 * nnz + 8.0 * (3 * n + 3 * n)
+    return {"workload": f"gap sweep, m=n={n} FP32 stored cost (1 GiB), after one pass",
+            "kernel": "gap_sweep_kernel<f32,4,2> (+ 40-byte readback copy)", "bound": "hbm",
+            "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS}
 
 
 def bench_batched(args):

@@ -132,6 +132,11 @@ int srot_step(srot_handle *h, int64_t nsteps, const int32_t *idx,
  * m int32) are optional per-row outputs g_i and j*_i.  Synchronises. */
 int srot_gap(srot_handle *h, double *out3, double *row_gap, int32_t *row_argmin);
 
+/* The same sweep as srot_gap, enqueued without synchronising: when the
+ * stream reaches it, out5 (device or pinned host memory, 5 doubles) receives
+ * {g, f, D, <T, C>, ||r||^2}.  Per-row outputs stay in the workspace. */
+int srot_gap_async(srot_handle *h, double *out5);
+
 /* Runs passes of m block steps, measuring the gap every opt->gap_every passes
  * and stopping at the first measurement with g <= opt->eps, or after
  * opt->max_passes passes (Sec. 3.1 stopping rule).

@@ -243,10 +243,23 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     if (e == hipSuccess) e = srot::launch_init_plan(h->P, h->S, h->stream);
     if (e == hipSuccess) e = srot::launch_residual(h->P, h->S, h->stream);
     if (e == hipSuccess) e = srot::launch_mask_build(h->P, h->S, h->stream);
+    // the FP32 LMO screen of wide fused rows needs an error bound (see the
+    // wide-row chain kernel): 8 u (Cmax + |w| Rmax), doubled, u = 2^-24
+    const bool wide = opt->cost == SROT_COST_SQEUCLID && !h->S.own.reg;
+    double bounds[2] = {0.0, 0.0};
+    if (e == hipSuccess && wide) e = srot::launch_screen_bounds(h->P, h->S.scalars + 5, h->stream);
+    if (e == hipSuccess && wide)
+        e = hipMemcpyAsync(bounds, h->S.scalars + 5, sizeof(bounds), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init: %s", hipGetErrorString(e));
     else if (flag & 1) rc = fail(SROT_ENONFINITE, "srot_init: NaN/Inf in C, X, Y, a or b, or a negative weight");
+    h->S.screen_delta2 = 0.0;
+    if (rc == SROT_OK && wide) {
+        const double u = 0x1.0p-24;
+        const double scale = bounds[0] + fabs(opt->w) * bounds[1];
+        h->S.screen_delta2 = 2.0 * (8.0 * u * scale) * (1.0 + 1e-6) + 1e-300;
+    }
     if (rc != SROT_OK) {
         free(h);
         return rc;
@@ -285,6 +298,14 @@ int srot_gap(srot_handle *h, double *out3, double *row_gap, int32_t *row_argmin)
     if (row_argmin)
         SROT_HIP(hipMemcpyAsync(row_argmin, h->S.row_j, sizeof(int32_t) * h->P.m, hipMemcpyDeviceToDevice, h->stream));
     if (row_gap || row_argmin) SROT_HIP(hipStreamSynchronize(h->stream));
+    return SROT_OK;
+}
+
+int srot_gap_async(srot_handle *h, double *out5)
+{
+    if (!h || !out5) return fail(SROT_EINVAL, "srot_gap_async: NULL argument");
+    SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
+    SROT_HIP(hipMemcpyAsync(out5, h->S.scalars, sizeof(double) * 5, hipMemcpyDefault, h->stream));
     return SROT_OK;
 }
 

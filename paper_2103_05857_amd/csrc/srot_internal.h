@@ -49,9 +49,10 @@ struct DeviceState {
     double *partials;      // gap_blocks x 4
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
-    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket
+    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep tickets, [4] gap-sweep ticket
     int64_t *resume;       // step at which the prefetching chain kernel stopped
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
+    double screen_delta2;  // 2 x error bound of the FP32 LMO screen (wide fused rows), 0 = unused
 };
 
 // Records a printf-style message as the calling thread's last error
@@ -80,6 +81,8 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
                         int64_t k0, int64_t nsteps, int rule, int32_t *trace_j,
                         double *trace_gamma, hipStream_t stream);
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+// {squared diameter of the points' bounding box, max(sum a, max b)} into out2.
+hipError_t launch_screen_bounds(const ProblemView &P, double *out2, hipStream_t stream);
 
 // Number of workgroups used by the gap sweep for an m-row problem.
 int32_t gap_blocks_for(int64_t m);

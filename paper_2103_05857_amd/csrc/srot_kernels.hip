@@ -162,6 +162,342 @@ __global__ __launch_bounds__(GLB_NT) void chain_glb_kernel(ProblemView P, double
 }
 
 // ---------------------------------------------------------------------------
+// Block-step chain for wide rows with the fused cost (4096 < n <= 32768).
+// One 512-thread workgroup; thread tid owns columns j = u * 512 + tid and
+// keeps their target points in registers.  The LMO is found in two stages:
+//   1. a screen in FP32: v'_j = fl(c'_j + w r32_j) with c'_j the FP32 squared
+//      distance and r32 an FP32 copy of r kept in LDS (owner-only access);
+//      every |v'_j - v_j| <= delta (bound below), so with m' = min_j v'_j
+//      every column whose exact value can reach the exact minimum satisfies
+//      v'_j <= m' + 2 delta;
+//   2. those candidates (typically one or two) are evaluated exactly in FP64
+//      (squared distance of the FP32 points in double, r_j from the FP64
+//      residual in global memory) and the lowest-index exact minimum wins.
+// The step is therefore exactly the FP64 BCFW step of Alg. 1.  Error bound
+// (u = 2^-24, round to nearest): the FP32 distance carries at most 5.01 u c,
+// the product w r at most 2.01 u |w r|, the final fused add u |v|; delta is
+// taken as 8 u (Cmax + |w| Rmax) with Cmax the squared diameter of the
+// points' bounding box and Rmax = max(sum a, max b) >= |r_j|, and the
+// threshold is rounded upwards.  The line search and the update run on the
+// row's support (bitmasks), as in the other chain kernels; r is updated in
+// FP64 (global) and its FP32 copy alongside.
+// ---------------------------------------------------------------------------
+constexpr int WIDE_NT = 512;
+constexpr int WIDE_KA = 2;
+constexpr int WIDE_MAX_N = WIDE_NT * 64;
+constexpr int WIDE_B = 8;  // columns per streamed batch  // support entries per thread read ahead of the screen
+
+__device__ __forceinline__ float wave_min_f32(float v)
+{
+    v = fminf(v, __int_as_float(dpp_i32<DPP_QUAD_XOR1>(__float_as_int(v))));
+    v = fminf(v, __int_as_float(dpp_i32<DPP_QUAD_XOR2>(__float_as_int(v))));
+    v = fminf(v, __int_as_float(dpp_i32<DPP_HALF_MIRROR>(__float_as_int(v))));
+    v = fminf(v, __int_as_float(dpp_i32<DPP_MIRROR>(__float_as_int(v))));
+    float m = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    m = fminf(m, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16)));
+    m = fminf(m, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)));
+    m = fminf(m, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
+    return m;
+}
+
+template <int CPTK, int YMODE, bool TRACE>
+__global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, double *__restrict__ T,
+                                                             double *__restrict__ rg,
+                                                             uint32_t *__restrict__ M, int words,
+                                                             const int32_t *__restrict__ idx, int64_t k0,
+                                                             int64_t nsteps, int rule,
+                                                             int32_t *__restrict__ trace_j,
+                                                             double *__restrict__ trace_gamma,
+                                                             double delta2)
+{
+    constexpr int NW = WIDE_NT / 64;
+    extern __shared__ float r32[];
+    __shared__ float s_m[2][NW];
+    __shared__ double s_v[2][NW];
+    __shared__ int s_j[2][NW];
+    __shared__ double s_sum[2][NW][3];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = P.n, m = P.m;
+    const double w = P.w;
+    const float w32 = (float)w;
+    const float4 *__restrict__ Y4 = P.Y4;
+
+    // r32 holds CPTK * WIDE_NT entries (zero past column n - 1), so the
+    // screen reads it at constant offsets; a column past n - 1 gets a point
+    // 3e18 away from every coordinate, whose screen value (~2.7e37, finite)
+    // never reaches the minimum of the real columns (every thread owns at
+    // least one real column: n > WIDE_NT)
+    // YMODE 1: the thread's target points in registers; 0: streamed from L2
+    constexpr int YR = YMODE == 1 ? CPTK : 1;
+    float y0[YR], y1[YR], y2[YR];
+#pragma unroll
+    for (int u = 0; u < CPTK; ++u) {
+        const int j = u * WIDE_NT + tid;
+        if constexpr (YMODE == 1) {
+            const float4 yv = Y4[j < n ? j : n - 1];
+            y0[u] = (j < n) ? yv.x : 3e18f;
+            y1[u] = (j < n) ? yv.y : 3e18f;
+            y2[u] = (j < n) ? yv.z : 3e18f;
+        }
+        r32[j] = (j < n) ? (float)rg[j] : 0.0f;
+    }
+
+    // row data of the next step (index, point, weight, this thread's mask
+    // words) is requested one step ahead; a mask is forwarded when the next
+    // step revisits the row just updated
+    const int64_t last = nsteps - 1;
+    int i_nx = idx[0];
+    int i_nn = idx[last > 0 ? 1 : 0];
+    double a_nx = P.a[i_nx];
+    float x_nx[3] = {P.X[3 * i_nx], P.X[3 * i_nx + 1], P.X[3 * i_nx + 2]};
+    uint32_t m_nx0 = M[(size_t)i_nx * words * WIDE_NT + tid];
+    uint32_t m_nx1 = words > 1 ? M[((size_t)i_nx * words + 1) * WIDE_NT + tid] : 0u;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int i = i_nx;
+        const double ai = a_nx;
+        const size_t base = (size_t)i * (size_t)n;
+        const float x0 = x_nx[0], x1 = x_nx[1], x2 = x_nx[2];
+        uint32_t *Mi = M + (size_t)i * words * WIDE_NT + tid;
+        const uint32_t mk0 = m_nx0;
+        const uint32_t mk1 = m_nx1;
+
+        // support entries at the WIDE_KA lowest mask bits: plan value, FP64
+        // residual and target point, requested before the screen
+        int aj[WIDE_KA];
+        double at[WIDE_KA], ar[WIDE_KA];
+        float ay[WIDE_KA][3];
+        uint32_t rest0 = mk0, rest1 = mk1;
+#pragma unroll
+        for (int k = 0; k < WIDE_KA; ++k) {
+            int u = -1;
+            if (rest0) { u = __ffs(rest0) - 1; rest0 &= rest0 - 1u; }
+            else if (rest1) { u = 32 + __ffs(rest1) - 1; rest1 &= rest1 - 1u; }
+            aj[k] = u >= 0 ? u * WIDE_NT + tid : -1;
+            const int jj = aj[k] >= 0 ? aj[k] : 0;
+            const double tv = T[base + jj];
+            at[k] = aj[k] >= 0 ? tv : 0.0;
+            ar[k] = rg[jj];
+            const float4 yv = Y4[jj];
+            ay[k][0] = yv.x; ay[k][1] = yv.y; ay[k][2] = yv.z;
+        }
+        const bool more = (rest0 | rest1) != 0u;
+
+        i_nx = i_nn;
+        i_nn = idx[s + 2 < last ? s + 2 : last];
+        a_nx = P.a[i_nx];
+        x_nx[0] = P.X[3 * i_nx]; x_nx[1] = P.X[3 * i_nx + 1]; x_nx[2] = P.X[3 * i_nx + 2];
+        m_nx0 = M[(size_t)i_nx * words * WIDE_NT + tid];
+        m_nx1 = words > 1 ? M[((size_t)i_nx * words + 1) * WIDE_NT + tid] : 0u;
+
+        // stage 1: FP32 screen, smallest and second smallest value per thread
+        float b1 = INFINITY, b2 = INFINITY;
+        int u1 = 0;
+        auto screen = [&](int u, float v) {
+            const bool lt = v < b1;
+            b2 = lt ? b1 : fminf(b2, v);
+            u1 = lt ? u : u1;
+            b1 = lt ? v : b1;
+        };
+        if constexpr (YMODE == 1) {
+#pragma unroll
+            for (int u = 0; u < CPTK; ++u) {
+                const float d0 = x0 - y0[u], d1 = x1 - y1[u], d2 = x2 - y2[u];
+                const float c = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+                screen(u, fmaf(w32, r32[u * WIDE_NT + tid], c));
+                __builtin_amdgcn_sched_barrier(0);  // the point registers stay the only per-column state
+            }
+        } else {
+            // points streamed from L2, WIDE_B columns per batch
+#pragma unroll 1
+            for (int ub = 0; ub < CPTK; ub += WIDE_B) {
+                float q0[WIDE_B], q1[WIDE_B], q2[WIDE_B];
+#pragma unroll
+                for (int e = 0; e < WIDE_B; ++e) {
+                    const int j = (ub + e) * WIDE_NT + tid;
+                    const float *yp = P.Y + 3 * (j < n ? j : n - 1);
+                    const bool real = j < n;
+                    q0[e] = real ? yp[0] : 3e18f;
+                    q1[e] = real ? yp[1] : 3e18f;
+                    q2[e] = real ? yp[2] : 3e18f;
+                }
+#pragma unroll
+                for (int e = 0; e < WIDE_B; ++e) {
+                    const float d0 = x0 - q0[e], d1 = x1 - q1[e], d2 = x2 - q2[e];
+                    const float c = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+                    screen(ub + e, fmaf(w32, r32[(ub + e) * WIDE_NT + tid], c));
+                }
+            }
+        }
+        const int j1 = u1 * WIDE_NT + tid;
+        const double r1 = rg[j1];
+        const float4 yb = Y4[j1];
+        float mw = wave_min_f32(b1);
+        if (lane == 0) s_m[s & 1][wid] = mw;
+        __syncthreads();
+        float mb = s_m[s & 1][0];
+#pragma unroll
+        for (int k = 1; k < NW; ++k) mb = fminf(mb, s_m[s & 1][k]);
+        const float thr = __double2float_ru((double)mb + delta2);
+
+        // stage 2: exact FP64 values of the candidates.  A thread with a single
+        // candidate evaluates it; one with several (rare) takes the exact
+        // minimum over all its columns, which contains them.
+        double best = INFINITY;
+        int bj = 0x7fffffff;
+        if (b1 <= thr) {
+            if (b2 <= thr) {
+                for (int j = tid; j < n; j += WIDE_NT) {
+                    const float4 yv = Y4[j];
+                    const double v = sqdist(x0, x1, x2, yv.x, yv.y, yv.z) + w * rg[j];
+                    if (v < best) { best = v; bj = j; }
+                }
+            } else {
+                best = sqdist(x0, x1, x2, yb.x, yb.y, yb.z) + w * r1;
+                bj = j1;
+            }
+        }
+        block_argmin<NW>(best, bj, s_v[s & 1], s_j[s & 1]);
+        const double G = best;
+        const int jstar = bj;
+
+        // line-search sums over this thread's support (Alg. 1 step size)
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < WIDE_KA; ++k) {
+            if (aj[k] >= 0) {
+                const double v = sqdist(x0, x1, x2, ay[k][0], ay[k][1], ay[k][2]) + w * ar[k];
+                const bool st = aj[k] == jstar;
+                acc[0] += at[k] * (v - G);
+                acc[1] += st ? 0.0 : at[k] * at[k];
+                acc[2] = st ? at[k] : acc[2];
+            }
+        }
+        if (more) {
+            uint32_t q0 = rest0, q1 = rest1;
+            while (q0 | q1) {
+                int u;
+                if (q0) { u = __ffs(q0) - 1; q0 &= q0 - 1u; }
+                else { u = 32 + __ffs(q1) - 1; q1 &= q1 - 1u; }
+                const int j = u * WIDE_NT + tid;
+                const double t = T[base + j];
+                const float4 yv = Y4[j];
+                const double v = sqdist(x0, x1, x2, yv.x, yv.y, yv.z) + w * rg[j];
+                const bool st = j == jstar;
+                acc[0] += t * (v - G);
+                acc[1] += st ? 0.0 : t * t;
+                acc[2] = st ? t : acc[2];
+            }
+        }
+        block_sum<NW, 3>(acc, s_sum[s & 1]);
+        const double gamma = step_size(rule, k0 + s, m, w, acc[0], acc[1], acc[2], ai);
+        const double gadd = gamma * ai;
+
+        // t_i <- (1 - gamma) t_i + gamma a_i e_j*, r <- r + (t_i new - t_i old)
+        uint32_t nm0 = mk0, nm1 = mk1;
+        bool star_in = false;
+        auto set_bit = [&](int u, bool on) {
+            if (u < 32) nm0 = on ? (nm0 | (1u << u)) : (nm0 & ~(1u << u));
+            else nm1 = on ? (nm1 | (1u << (u - 32))) : (nm1 & ~(1u << (u - 32)));
+        };
+#pragma unroll
+        for (int k = 0; k < WIDE_KA; ++k) {
+            if (aj[k] >= 0) {
+                const bool st = aj[k] == jstar;
+                star_in |= st;
+                const double tn = blend(at[k], gamma, st ? gadd : 0.0);
+                if (tn != at[k]) {
+                    T[base + aj[k]] = tn;
+                    const double rn = ar[k] + (tn - at[k]);
+                    rg[aj[k]] = rn;
+                    r32[aj[k]] = (float)rn;
+                }
+                set_bit(aj[k] / WIDE_NT, tn != 0.0);
+            }
+        }
+        if (more) {
+            uint32_t q0 = rest0, q1 = rest1;
+            while (q0 | q1) {
+                int u;
+                if (q0) { u = __ffs(q0) - 1; q0 &= q0 - 1u; }
+                else { u = 32 + __ffs(q1) - 1; q1 &= q1 - 1u; }
+                const int j = u * WIDE_NT + tid;
+                const double t = T[base + j];
+                const bool st = j == jstar;
+                star_in |= st;
+                const double tn = blend(t, gamma, st ? gadd : 0.0);
+                if (tn != t) {
+                    T[base + j] = tn;
+                    const double rn = rg[j] + (tn - t);
+                    rg[j] = rn;
+                    r32[j] = (float)rn;
+                }
+                set_bit(u, tn != 0.0);
+            }
+        }
+        if ((jstar % WIDE_NT) == tid && !star_in) {
+            const double tsn = blend(0.0, gamma, gadd);
+            if (tsn != 0.0) {
+                T[base + jstar] = tsn;
+                const double rn = rg[jstar] + tsn;
+                rg[jstar] = rn;
+                r32[jstar] = (float)rn;
+                set_bit(jstar / WIDE_NT, true);
+            }
+        }
+        if (nm0 != mk0) Mi[0] = nm0;
+        if (words > 1 && nm1 != mk1) Mi[WIDE_NT] = nm1;
+        if (i_nx == i) { m_nx0 = nm0; m_nx1 = nm1; }
+        if constexpr (TRACE) {
+            if (tid == 0) {
+                if (trace_j) trace_j[s] = jstar;
+                if (trace_gamma) trace_gamma[s] = gamma;
+            }
+        }
+    }
+}
+
+// Bounds used by the wide-row screen: bounding box of all points and
+// max(sum a, max b).  One workgroup; out = {sq. box diameter, Rmax}.
+__global__ __launch_bounds__(256) void screen_bounds_kernel(ProblemView P, double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double lo[3], hi[3], sa = 0.0, mb = 0.0;
+    for (int d = 0; d < 3; ++d) { lo[d] = INFINITY; hi[d] = -INFINITY; }
+    for (int i = threadIdx.x; i < P.m; i += 256) {
+        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], (double)P.X[3 * i + d]); hi[d] = fmax(hi[d], (double)P.X[3 * i + d]); }
+        sa += P.a[i];
+    }
+    for (int j = threadIdx.x; j < P.n; j += 256) {
+        for (int d = 0; d < 3; ++d) { lo[d] = fmin(lo[d], (double)P.Y[3 * j + d]); hi[d] = fmax(hi[d], (double)P.Y[3 * j + d]); }
+        mb = fmax(mb, P.b[j]);
+    }
+    auto reduce = [&](double v, int op) -> double {  // 0: min, 1: max, 2: sum
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                const double o = sh[threadIdx.x + s];
+                sh[threadIdx.x] = op == 0 ? fmin(sh[threadIdx.x], o) : (op == 1 ? fmax(sh[threadIdx.x], o) : sh[threadIdx.x] + o);
+            }
+            __syncthreads();
+        }
+        const double r = sh[0];
+        __syncthreads();
+        return r;
+    };
+    double diam2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double l = reduce(lo[d], 0), h = reduce(hi[d], 1);
+        diam2 += (h - l) * (h - l);
+    }
+    const double suma = reduce(sa, 2), maxb = reduce(mb, 1);
+    if (threadIdx.x == 0) {
+        out[0] = diam2;
+        out[1] = fmax(suma, maxb);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Gap sweep (Thm 2, eq. AppenEq:Gi, dual of App. D), streaming the cost once.
 // A wave takes R rows at a time (row groups strided over the grid), with no
 // workgroup barrier per row:
@@ -720,8 +1056,40 @@ static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, 
 #undef SROT_CHAIN
         return hipErrorInvalidConfiguration;
     }
+    if constexpr (COST == SROT_COST_SQEUCLID) {
+        if (P.n <= WIDE_MAX_N && S.screen_delta2 > 0.0) {
+            const size_t lds = sizeof(float) * (size_t)WIDE_NT * (o.cpt <= 16 ? 16 : (o.cpt <= 32 ? 32 : 64));
+#define SROT_WIDE(CPTK_, YMODE_)                                                                    \
+            if (o.cpt <= CPTK_) {                                                                  \
+                const void *fn = (tj || tg) ? (const void *)&chain_wide_kernel<CPTK_, YMODE_, true>   \
+                                            : (const void *)&chain_wide_kernel<CPTK_, YMODE_, false>; \
+                hipError_t e_ = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                                                    (int)lds);                                       \
+                if (e_ != hipSuccess) return e_;                                                   \
+                if (tj || tg)                                                                      \
+                    hipLaunchKernelGGL((chain_wide_kernel<CPTK_, YMODE_, true>), dim3(1), dim3(WIDE_NT), \
+                                       lds, st, P, S.T, S.r, S.mask, o.words, idx, k0, nsteps, rule, tj, \
+                                       tg, S.screen_delta2);                                       \
+                else                                                                               \
+                    hipLaunchKernelGGL((chain_wide_kernel<CPTK_, YMODE_, false>), dim3(1), dim3(WIDE_NT), \
+                                       lds, st, P, S.T, S.r, S.mask, o.words, idx, k0, nsteps, rule, tj, \
+                                       tg, S.screen_delta2);                                       \
+                return hipGetLastError();                                                          \
+            }
+            SROT_WIDE(16, 1)
+            SROT_WIDE(32, 1)
+            SROT_WIDE(64, 0)
+#undef SROT_WIDE
+        }
+    }
     hipLaunchKernelGGL((chain_glb_kernel<COST>), dim3(1), dim3(GLB_NT), 0, st, P, S.T, S.r, S.mask,
                        o.words, idx, k0, nsteps, rule, tj, tg);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_bounds(const ProblemView &P, double *out2, hipStream_t stream)
+{
+    hipLaunchKernelGGL(screen_bounds_kernel, dim3(1), dim3(256), 0, stream, P, out2);
     return hipGetLastError();
 }
 

@@ -67,6 +67,8 @@ def load():
     L.srot_step.restype = ctypes.c_int
     L.srot_gap.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _vp, _vp]
     L.srot_gap.restype = ctypes.c_int
+    L.srot_gap_async.argtypes = [_vp, _vp]
+    L.srot_gap_async.restype = ctypes.c_int
     L.srot_solve.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     L.srot_solve.restype = ctypes.c_int
     L.srot_get_plan.argtypes = [_vp, _vp, _vp]
@@ -143,6 +145,12 @@ def srot_gap(h, row_gap=None, row_argmin=None):
     out = (ctypes.c_double * 3)()
     _check(load().srot_gap(h, out, _ptr(row_gap), _ptr(row_argmin)))
     return out[0], out[1], out[2]
+
+
+def srot_gap_async(h, out5):
+    """Enqueues the gap sweep; out5 (5 doubles, device or pinned) receives
+    {g, f, D, <T,C>, ||r||^2} when the stream gets there."""
+    _check(load().srot_gap_async(h, _ptr(out5)))
 
 
 def srot_solve(h):

@@ -90,7 +90,10 @@ def _close_fg(gpu, ref):
     ("stored", np.float32, 97, 4096, 1.0),      # full row width of the 4096 config
     ("sqeuclid", None, 200, 777, 1.0),
     ("stored", np.float32, 41, 5000, 1.0),      # global-residual kernel
-    ("sqeuclid", None, 37, 6001, 3.0),
+    ("sqeuclid", None, 37, 6001, 3.0),          # wide rows: FP32 screen, points in registers
+    ("sqeuclid", None, 23, 12001, 1.0),         # wide rows, 32 columns per thread
+    ("sqeuclid", None, 11, 20000, 0.5),         # wide rows, points streamed from L2
+    ("sqeuclid", None, 5, 32768, 10.0),         # the widest screened row
 ])
 def test_trace_parity_explicit_indices(cost_mode, dtype, m, n, w):
     _need_gpu()
@@ -243,6 +246,34 @@ def test_exact_ties_pick_lowest_column():
                 checked += 1
             touched.add(int(otr[0][k]))
         assert checked > 0
+
+
+@pytest.mark.parametrize("n", [9000, 20000])
+def test_wide_rows_with_repeated_points_in_one_thread(n):
+    """Wide fused rows where one thread owns several columns with the same
+    target point (columns j and j + 512 k): equal cost entries, so its FP32
+    screen has several candidates and the exact FP64 pass over all its
+    columns decides; the lowest index must win while the twins are untouched."""
+    _need_gpu()
+    m = 24
+    X = I.mixture_points(3, m)
+    Y = I.mixture_points(4, n)
+    for k in range(1, 4):
+        Y[512 * k: 512 * k + 64] = Y[0:64]
+    b = I.uniform_weights(n)
+    d = dict(X=X, Y=Y, a=I.uniform_weights(m), b=b)
+    idx = I.philox_uniform_indices(9, 0, m * 8, m)
+    P = _oracle_problem(d, "sqeuclid", 1.0)
+    st = O.State(P)
+    otr = O.bcfw_steps(P, st, idx)
+    sol = _gpu_problem(d, "sqeuclid", 1.0)
+    gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
+    gjn = gj.cpu().numpy()
+    diff = np.nonzero(gjn != otr[0])[0]
+    first = int(diff[0]) if len(diff) else len(idx)
+    if first < len(idx):
+        assert otr[2][first] <= 1e-12          # diverged only at a tie
+    np.testing.assert_allclose(gg.cpu().numpy()[:first], otr[1][:first], rtol=0, atol=1e-9)
 
 
 def test_resume_from_checkpoint_repeats_the_run():
