@@ -25,16 +25,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNELS_SRC = os.path.join(ROOT, "paper_2103_05857_amd", "csrc", "srot_kernels.hip")
 PROFILE = os.path.join(ROOT, "profiles", "chain_gap_stored_f32_m4096_n4096.md")
+SWEEP_PROFILE = os.path.join(ROOT, "profiles", "gap_sweep_stored_f32_m16384_n16384.md")
 
 
-def counter_traffic(kernel_prefix):
+def counter_traffic(kernel_prefix, profile=PROFILE, grid=None):
     """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel factors), or
     None when the summary is absent or the kernel source changed since."""
     import hashlib
     import re
     try:
-        text = open(PROFILE).read()
+        text = open(profile).read()
         blob = json.loads(re.findall(r"```json\n(.*?)\n```", text, flags=re.S)[-1])
         sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()[:16]
     except (OSError, IndexError, ValueError):
@@ -42,7 +43,7 @@ def counter_traffic(kernel_prefix):
     if blob.get("kernels_sha256") != sha:
         return None
     for name, v in blob["per_dispatch"].items():
-        if name.startswith(kernel_prefix):
+        if name.startswith(kernel_prefix) and (grid is None or name.endswith(f"[grid {grid}]")):
             return 1024.0 * (v["fetch_kib"] * blob["fetch_scale"] + v["write_kib"] * blob["write_scale"])
     return None
 
@@ -238,7 +239,8 @@ def bench_sweep(args):
     return {"workload": f"gap sweep, m=n={n} FP32 stored cost (1 GiB), after one pass",
             "kernel": "gap_sweep_kernel<f32,4,2> (+ 40-byte readback copy)", "bound": "hbm",
             "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS}
+            "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS,
+            "traffic": counter_traffic("srot::gap_sweep_kernel<0, 4, 2>", SWEEP_PROFILE, grid=1024 * 256)}
 
 
 def bench_batched(args):
