@@ -239,3 +239,17 @@ def fw_iteration(P, T, k, rule=ELS):
     gam = ctypes.c_double()
     g = _load().or_fw_iteration(P.ref, _ptr(T, ctypes.c_double), int(k), int(rule), ctypes.byref(gam))
     return g, gam.value
+
+
+def barycentric(T, X, Y):
+    """Barycentric projection (eq. barycentric_projection, Sec. 5):
+    xhat_i = sum_j t_ij y_j / sum_j t_ij in FP64; a row without mass keeps x_i."""
+    T = np.asarray(T, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    out = X.copy()
+    for i in range(T.shape[0]):
+        den = T[i].sum()
+        if den > 0.0:
+            out[i] = (T[i][:, None] * Y).sum(axis=0) / den
+    return out
