@@ -185,6 +185,29 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
 int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *dY,
                   double *da, double *db);
 
+/* Full Frank-Wolfe (Alg. A.1) on the handle's plan: each iteration takes
+ * every row's LMO vertex at once (S = (a_i e_{j*_i})_i, from the gap sweep),
+ * and moves T <- (1 - gamma) T + gamma S with the decay step 2/(k+2) (k =
+ * FW iteration counter of the handle, from 0) or the exact line search of
+ * eq. AppenEq:SemiRelaxedFWStep, gamma = clip(<T - S, grad f> /
+ * (w ||(T - S)^T 1||^2), 0, 1), as opt->step_rule says.  Shares the plan,
+ * residual and masks with the block-coordinate entry points.
+ *   iters        number of iterations (enqueued; no synchronisation).
+ *   trace_gamma  device, iters doubles (optional): the step sizes. */
+int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma);
+
+/* Full Frank-Wolfe until the gap measured at an iterate is <= opt->eps or
+ * opt->max_passes iterations have run.  out3 (host) = {g, f, D} at the last
+ * iterate; *iters (host) = iterations run.  Synchronises every iteration.
+ * Returns SROT_OK or SROT_NOT_CONVERGED. */
+int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters);
+
+/* Barycentric projection of the source points through the plan
+ * (eq. barycentric_projection): Xhat_i = sum_j t_ij y_j / sum_j t_ij
+ * (device, m x 3 float; a row without mass keeps x_i).  Needs X and Y at
+ * srot_init.  Enqueued on the stream. */
+int srot_barycentric(srot_handle *h, float *Xhat);
+
 /* ------------------------------------------------------------------------
  * Batched solver: many independent problems of uneven sizes, each solved
  * from the initial plan to g <= eps (or max_passes) by Alg. 1 with the

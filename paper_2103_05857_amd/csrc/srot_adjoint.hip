@@ -208,7 +208,61 @@ __global__ __launch_bounds__(ADJ_NT) void adjoint_final_kernel(ProblemView P, co
     }
 }
 
+// Barycentric projection (eq. barycentric_projection): one workgroup per
+// row, FP64 sums over the support in a fixed order.  A row without mass
+// keeps its own point.
+__global__ __launch_bounds__(ADJ_NT) void barycentric_kernel(ProblemView P, const double *__restrict__ T,
+                                                             const uint32_t *__restrict__ M, Ownership own,
+                                                             float *__restrict__ Xhat)
+{
+    __shared__ double sh[4][ADJ_NT];
+    const int tid = threadIdx.x;
+    const int n = P.n;
+    const int slots = own.words * own.nt;
+    for (int i = blockIdx.x; i < P.m; i += gridDim.x) {
+        const size_t base = (size_t)i * (size_t)n;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = tid; s < slots; s += ADJ_NT) {
+            const int wd = s / own.nt, ts = s - wd * own.nt;
+            uint32_t mk = M[(size_t)i * slots + s];
+            while (mk) {
+                const int bt = __ffs(mk) - 1;
+                mk &= mk - 1u;
+                const int j = own_col(own, wd * 32 + bt, ts);
+                const double t = T[base + j];
+                acc[0] += t * (double)P.Y[3 * j];
+                acc[1] += t * (double)P.Y[3 * j + 1];
+                acc[2] += t * (double)P.Y[3 * j + 2];
+                acc[3] += t;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) sh[d][tid] = acc[d];
+        __syncthreads();
+        for (int h = ADJ_NT / 2; h > 0; h >>= 1) {
+            if (tid < h) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) sh[d][tid] += sh[d][tid + h];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const double den = sh[3][0];
+            for (int d = 0; d < 3; ++d)
+                Xhat[3 * i + d] = den > 0.0 ? (float)(sh[d][0] / den) : P.X[3 * i + d];
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+hipError_t launch_barycentric(const ProblemView &P, const DeviceState &S, float *Xhat, hipStream_t stream)
+{
+    hipLaunchKernelGGL(barycentric_kernel, dim3((int)std::min<int64_t>(P.m, 4096)), dim3(ADJ_NT), 0, stream, P,
+                       (const double *)S.T, (const uint32_t *)S.mask, S.own, Xhat);
+    return hipGetLastError();
+}
 
 int32_t adjoint_slices_cap(int64_t m) { return (int32_t)std::min<int64_t>(m, 32); }
 

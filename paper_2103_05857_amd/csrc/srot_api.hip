@@ -18,7 +18,8 @@ struct srot_handle {
     srot::DeviceState S;
     srot_options opt;
     hipStream_t stream;
-    int64_t k;  // global block-step counter (decay rule, sampler position)
+    int64_t k;     // global block-step counter (decay rule, sampler position)
+    int64_t fw_k;  // full Frank-Wolfe iteration counter (decay rule of Alg. A.1)
 };
 
 namespace {
@@ -86,7 +87,8 @@ Layout make_layout(int64_t m, int64_t n)
     L.G = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.j = off; off = align_up(off + sizeof(int32_t) * (size_t)m);
     L.g = off; off = align_up(off + sizeof(double) * (size_t)m);
-    L.partials = off; off = align_up(off + sizeof(double) * 4 * (size_t)L.gap_blocks);
+    L.partials = off;
+    off = align_up(off + sizeof(double) * std::max<size_t>(4 * (size_t)L.gap_blocks, (size_t)srot::fw_finish_blocks(n)));
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.resume = off; off = align_up(off + sizeof(int64_t));
@@ -208,6 +210,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->opt = *opt;
     h->stream = (hipStream_t)stream;
     h->k = 0;
+    h->fw_k = 0;
     h->P.m = (int32_t)m;
     h->P.n = (int32_t)n;
     h->P.cost = opt->cost;
@@ -372,6 +375,41 @@ int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *d
         return fail(SROT_EINVAL, "srot_backward: dX and dY need the points X and Y given to srot_init");
     if (da) SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));  // row minima of the gradient
     SROT_HIP(srot::launch_adjoint(h->P, h->S, grad_out, dC, dX, dY, da, db, h->stream));
+    return SROT_OK;
+}
+
+int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma)
+{
+    if (!h) return fail(SROT_EINVAL, "srot_fw_steps: NULL handle");
+    if (iters < 0) return fail(SROT_EINVAL, "srot_fw_steps: iters < 0");
+    for (int64_t it = 0; it < iters; ++it) {
+        SROT_HIP(srot::launch_fw_step(h->P, h->S, h->fw_k, h->opt.step_rule,
+                                      trace_gamma ? trace_gamma + it : nullptr, h->stream));
+        h->fw_k += 1;
+    }
+    return SROT_OK;
+}
+
+int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters)
+{
+    if (!h || !out3 || !iters) return fail(SROT_EINVAL, "srot_fw_solve: NULL argument");
+    *iters = 0;
+    for (int64_t it = 0;; ++it) {
+        int rc = measure_gap(h, out3);  // the sweep also gives every row's vertex
+        if (rc != SROT_OK) return rc;
+        if (out3[0] <= h->opt.eps) return SROT_OK;
+        if (it >= h->opt.max_passes) return SROT_NOT_CONVERGED;
+        SROT_HIP(srot::launch_fw_update(h->P, h->S, h->fw_k, h->opt.step_rule, nullptr, h->stream));
+        h->fw_k += 1;
+        *iters = it + 1;
+    }
+}
+
+int srot_barycentric(srot_handle *h, float *Xhat)
+{
+    if (!h || !Xhat) return fail(SROT_EINVAL, "srot_barycentric: NULL argument");
+    if (!h->P.X || !h->P.Y) return fail(SROT_EINVAL, "srot_barycentric: needs the points X and Y given to srot_init");
+    SROT_HIP(srot::launch_barycentric(h->P, h->S, Xhat, h->stream));
     return SROT_OK;
 }
 

@@ -49,7 +49,7 @@ struct DeviceState {
     double *partials;      // gap_blocks x 4
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
-    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep tickets, [4] gap-sweep ticket
+    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW tickets, [4] gap-sweep ticket
     int64_t *resume;       // step at which the prefetching chain kernel stopped
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
     double screen_delta2;  // 2 x error bound of the FP32 LMO screen (wide fused rows), 0 = unused
@@ -94,5 +94,20 @@ hipError_t launch_adjoint(const ProblemView &P, const DeviceState &S, double g, 
                           float *dX, float *dY, double *da, double *db, hipStream_t stream);
 // Row slices of the adjoint's column sums (sizes DeviceState::adj_part).
 int32_t adjoint_slices_cap(int64_t m);
+
+// Full Frank-Wolfe iteration (srot_fw.hip): launch_fw_update runs the vertex
+// column sums, the step size (scalars[5]) and the update after a gap sweep;
+// launch_fw_step is the sweep followed by the update.  trace_gamma (device,
+// optional) receives this iteration's step size.  k: FW iteration counter.
+hipError_t launch_fw_update(const ProblemView &P, const DeviceState &S, int64_t k, int rule,
+                            double *trace_gamma, hipStream_t stream);
+hipError_t launch_fw_step(const ProblemView &P, const DeviceState &S, int64_t k, int rule,
+                          double *trace_gamma, hipStream_t stream);
+// Workgroups of the FW step-size reduction (the gap partial buffer holds
+// at least this many doubles).
+int32_t fw_finish_blocks(int64_t n);
+
+// Barycentric projection (srot_adjoint.hip): Xhat_i = sum_j t_ij y_j / sum_j t_ij.
+hipError_t launch_barycentric(const ProblemView &P, const DeviceState &S, float *Xhat, hipStream_t stream);
 
 }  // namespace srot

@@ -92,6 +92,12 @@ def load():
     L.srot_get_tiles_batched.restype = ctypes.c_int
     L.srot_destroy_batched.argtypes = [_vp]
     L.srot_destroy_batched.restype = None
+    L.srot_fw_steps.argtypes = [_vp, _i64, _vp]
+    L.srot_fw_steps.restype = ctypes.c_int
+    L.srot_fw_solve.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    L.srot_fw_solve.restype = ctypes.c_int
+    L.srot_barycentric.argtypes = [_vp, _vp]
+    L.srot_barycentric.restype = ctypes.c_int
     L.srot_destroy.argtypes = [_vp]
     L.srot_destroy.restype = None
     L.srot_strerror.argtypes = [ctypes.c_int]
@@ -176,6 +182,21 @@ def srot_set_state(h, T_in, k, r_in=None):
 
 def srot_backward(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):
     _check(load().srot_backward(h, float(grad_out), _ptr(dC), _ptr(dX), _ptr(dY), _ptr(da), _ptr(db)))
+
+
+def srot_fw_steps(h, iters, trace_gamma=None):
+    _check(load().srot_fw_steps(h, int(iters), _ptr(trace_gamma)))
+
+
+def srot_fw_solve(h):
+    out = (ctypes.c_double * 3)()
+    iters = _i64()
+    st = _check(load().srot_fw_solve(h, out, ctypes.byref(iters)), allow=(SROT_OK, SROT_NOT_CONVERGED))
+    return st, (out[0], out[1], out[2]), iters.value
+
+
+def srot_barycentric(h, Xhat):
+    _check(load().srot_barycentric(h, _ptr(Xhat)))
 
 
 def srot_destroy(h):

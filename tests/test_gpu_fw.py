@@ -1,0 +1,144 @@
+"""Full Frank-Wolfe (Alg. A.1) and the barycentric projection on the GPU,
+against the FP64 oracle.
+
+Bar: step sizes within 1e-9 absolute per iteration; the plan within 1e-9
+absolute; f within 1e-6 relative and g within 1e-6 * max(g, 1e-9) + 1e-15
+(the tolerance of the block-coordinate parity tests); the projection within
+one FP32 rounding (1e-6 relative to the coordinates' magnitude).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as A
+from oracle import oracle as O
+from paper_2103_05857_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _S():
+    from paper_2103_05857_amd import srot as S
+    return S
+
+
+def _solver(d, cost_mode, w, **opts):
+    S = _S()
+    a = torch.from_numpy(d["a"]).to(DEV)
+    b = torch.from_numpy(d["b"]).to(DEV)
+    X = torch.from_numpy(d["X"]).to(DEV)
+    Y = torch.from_numpy(d["Y"]).to(DEV)
+    if cost_mode == "sqeuclid":
+        return S.Solver(a, b, X=X, Y=Y, w=w, **opts)
+    return S.Solver(a, b, C=torch.from_numpy(d["C"]).to(DEV), X=X, Y=Y, w=w, **opts)
+
+
+def _oracle(d, cost_mode, w):
+    if cost_mode == "sqeuclid":
+        return O.Problem(d["a"], d["b"], w, X=d["X"], Y=d["Y"])
+    return O.Problem(d["a"], d["b"], w, C=d["C"].astype(np.float64))
+
+
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w,rule", [
+    ("stored", np.float64, 64, 96, 1.0, 0),
+    ("stored", np.float32, 300, 700, 0.5, 0),
+    ("sqeuclid", None, 200, 333, 2.0, 1),
+    ("stored", np.float32, 41, 5000, 1.0, 0),       # wide-row ownership
+    ("sqeuclid", None, 19, 9000, 1.0, 0),           # wide fused rows
+])
+def test_fw_iterations_match_oracle(cost_mode, dtype, m, n, w, rule):
+    S = _S()
+    d = I.problem_mixture(6, m, n, cost_dtype=dtype or np.float32)
+    P = _oracle(d, cost_mode, w)
+    T = O.init_plan(P)
+    K = 25
+    og = []
+    for k in range(K):
+        _, gam = O.fw_iteration(P, T, k, rule=rule)
+        og.append(gam)
+    ref = O.gap(P, T)
+    sol = _solver(d, cost_mode, w, step_rule=rule)
+    tg = torch.empty(K, dtype=torch.float64, device=DEV)
+    S.srot_fw_steps(sol.h, K, tg)
+    g, f, D = sol.gap()
+    Tg, r = sol.plan()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(tg.cpu().numpy(), og, rtol=0, atol=1e-9)
+    Tg = Tg.cpu().numpy()
+    np.testing.assert_allclose(Tg, T, rtol=0, atol=1e-9)
+    assert Tg.min() >= 0.0
+    np.testing.assert_allclose(r.cpu().numpy(), Tg.sum(axis=0) - d["b"], rtol=0, atol=1e-12)
+    assert abs(f - ref["f"]) <= 1e-6 * abs(ref["f"]) + 1e-15
+    assert abs(g - ref["g"]) <= 1e-6 * max(ref["g"], 1e-9) + 1e-15
+    sol.close()
+
+
+def test_fw_and_block_steps_share_the_state():
+    """Block steps, then full FW iterations, then block steps again: the
+    support masks written by either path are read correctly by the other.
+    The decay rule is used throughout: exact line search leaves a row's atoms
+    at equal gradient values (rounding-level LMO ties, where either column is
+    a correct answer), which would let the two sides take different but
+    equally valid FW vertices."""
+    S = _S()
+    m, n, w = 80, 120, 1.0
+    d = I.problem_mixture(7, m, n, cost_dtype=np.float64)
+    P = _oracle(d, "stored", w)
+    st = O.State(P)
+    i1 = I.philox_uniform_indices(3, 0, 2 * m, m)
+    i2 = I.philox_uniform_indices(3, 2 * m, 2 * m, m)
+    O.bcfw_steps(P, st, i1, rule=O.DEC, trace=False)
+    ogam = []
+    for k in range(6):
+        _, gam = O.fw_iteration(P, st.T, k, rule=O.DEC)
+        ogam.append(gam)
+    st.r = O.residual(P, st.T)
+    otr = O.bcfw_steps(P, st, i2, rule=O.DEC)
+    ref = O.gap(P, st.T)
+
+    sol = _solver(d, "stored", w, step_rule=S.SROT_DEC)
+    sol.step(len(i1), idx=torch.from_numpy(i1).to(DEV))
+    tg = torch.empty(6, dtype=torch.float64, device=DEV)
+    S.srot_fw_steps(sol.h, 6, tg)
+    gj, gg = sol.step(len(i2), idx=torch.from_numpy(i2).to(DEV), trace=True)
+    g, f, D = sol.gap()
+    T, _ = sol.plan()
+    np.testing.assert_allclose(tg.cpu().numpy(), ogam, rtol=0, atol=1e-15)
+    assert np.array_equal(gj.cpu().numpy(), otr[0])
+    np.testing.assert_allclose(gg.cpu().numpy(), otr[1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(T.cpu().numpy(), st.T, rtol=0, atol=1e-9)
+    assert abs(f - ref["f"]) <= 1e-6 * abs(ref["f"])
+    sol.close()
+
+
+def test_fw_solve_reaches_the_gap_and_brackets_the_optimum():
+    S = _S()
+    m, n, w = 48, 64, 1.0
+    d = I.problem_mixture(8, m, n, cost_dtype=np.float64)
+    sol = _solver(d, "stored", w, eps=1e-5, max_passes=20000)
+    st, (g, f, D), iters = S.srot_fw_solve(sol.h)
+    sol.close()
+    assert st == S.SROT_OK and g <= 1e-5 and iters > 0
+    P = _oracle(d, "stored", w)
+    ost, _ = O.solve(P, lambda p: I.philox_uniform_indices(0, p * m, m, m), max_passes=1500, gap_every=1500)
+    Ts, _, _ = A.kkt_polish(d["C"], d["a"], d["b"], w, ost.T)
+    fstar = A.objective(d["C"], d["b"], w, Ts)
+    assert D <= fstar + 1e-12 and fstar <= f + 1e-12      # weak duality bracket
+    assert f - fstar <= g + 1e-12
+
+
+@pytest.mark.parametrize("cost_mode,m,n", [("stored", 64, 96), ("sqeuclid", 37, 6001)])
+def test_barycentric_projection_matches_oracle(cost_mode, m, n):
+    S = _S()
+    d = I.problem_mixture(9, m, n, cost_dtype=np.float64)
+    sol = _solver(d, cost_mode, 1.0, seed=2)
+    sol.step(10 * m)
+    T, _ = sol.plan()
+    Xh = torch.empty(m, 3, dtype=torch.float32, device=DEV)
+    S.srot_barycentric(sol.h, Xh)
+    torch.cuda.synchronize()
+    ref = O.barycentric(T.cpu().numpy(), d["X"], d["Y"])
+    np.testing.assert_allclose(Xh.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+    sol.close()
