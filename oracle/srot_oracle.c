@@ -264,6 +264,133 @@ int or_bcfw_steps(const or_problem *P, double *T, double *r, int64_t *k,
     return 0;
 }
 
+/* Block-coordinate Frank-Wolfe with away steps (Alg. A.2, BCAFW, pairwise =
+ * 0) or pairwise steps (Alg. A.3, BCPFW, pairwise = 1), Sec. 4.1.  A block
+ * t_i in a_i * simplex is the combination sum_j alpha_j (a_i e_j) with
+ * alpha_j = t_ij / a_i; its active set is the support {j : t_ij > 0}.  Per
+ * step, with g = grad_i f (eq. RelaxedGradient):
+ *   FW vertex    s = a_i e_js,  js = lowest-index argmin of g;
+ *   away vertex  v = a_i e_ja,  ja = argmax of g over the active set
+ *                (lowest index on ties);
+ *   BCAFW: d_FW = s - t_i, d_A = t_i - v; the FW direction is taken when
+ *          <-g, d_FW> >= <-g, d_A>, with gamma_max = 1, else the away
+ *          direction with gamma_max = alpha_ja / (1 - alpha_ja).  With a
+ *          single atom, or ja = js, d_A is zero in exact arithmetic (alpha
+ *          is 1 only up to rounding) and the FW direction is taken;
+ *   BCPFW: d = s - v, gamma_max = alpha_ja.
+ * Line search (eq. SemiRelaxedBCAFWStep in the penalty-weight form): f is
+ * quadratic along d with curvature w ||d||^2, so gamma = -<g, d> / (w ||d||^2)
+ * clipped to [0, gamma_max] (gamma_max when the curvature vanishes and the
+ * slope is negative; 0 when the slope is not negative).  A step that reaches
+ * gamma_max on an away or pairwise direction removes atom ja: its entry is
+ * set to exactly 0.  Updates: FW direction (1 - gamma) t + gamma s (as
+ * or_bcfw_steps), away direction (1 + gamma) t - gamma v, pairwise t_js +=
+ * gamma a_i, t_ja -= gamma a_i; r follows the changed entries.
+ * Traces (each optional): tr_j = js; tr_away = ja (BCAFW: -1 - ja when the
+ * FW direction was taken); tr_gamma; tr_margin / tr_near as in
+ * or_bcfw_steps; tr_amargin = largest minus second-largest gradient value on
+ * the active set (INFINITY with one atom) and tr_anear = the first four
+ * active columns within near_tol of the largest (-1 padded). */
+int or_active_steps(const or_problem *P, double *T, double *r, int64_t *k, int pairwise,
+                    int64_t nsteps, const int32_t *idx, int32_t *tr_j, int32_t *tr_away,
+                    double *tr_gamma, double *tr_margin, int32_t *tr_near,
+                    double *tr_amargin, int32_t *tr_anear, double near_tol)
+{
+    const int64_t m = P->m, n = P->n;
+    double *grad = (double *)malloc(sizeof(double) * (size_t)n);
+    double *d = (double *)malloc(sizeof(double) * (size_t)n);
+    double *old = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int64_t st = 0; st < nsteps; ++st) {
+        int64_t i = idx[st];
+        if (i < 0 || i >= m) { free(grad); free(d); free(old); return -1; }
+        double *t_i = T + i * n;
+        const double ai = P->a[i];
+        or_block_gradient(P, r, i, grad);
+        double margin;
+        int64_t runner;
+        int64_t js = or_lmo2(n, grad, &margin, &runner);
+        int64_t ja = -1, natoms = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (t_i[j] > 0.0) {
+                ++natoms;
+                if (ja < 0 || grad[j] > grad[ja]) ja = j;
+            }
+        double gamma = 0.0;
+        int fw_dir = 0, drop = 0;
+        for (int64_t j = 0; j < n; ++j) old[j] = t_i[j];
+        if (ja >= 0) {
+            const double alpha = t_i[ja] / ai;
+            double gmax;
+            if (pairwise) {
+                for (int64_t j = 0; j < n; ++j) d[j] = (j == js ? ai : 0.0) - (j == ja ? ai : 0.0);
+                gmax = alpha;
+            } else {
+                double slope_fw = 0.0, slope_aw = 0.0;   /* <-g, d_FW>, <-g, d_A> */
+                for (int64_t j = 0; j < n; ++j) {
+                    slope_fw -= grad[j] * ((j == js ? ai : 0.0) - t_i[j]);
+                    slope_aw -= grad[j] * (t_i[j] - (j == ja ? ai : 0.0));
+                }
+                /* with one atom, or the away vertex at the FW vertex, the away
+                 * direction is zero in exact arithmetic: take the FW one */
+                fw_dir = natoms == 1 || ja == js || slope_fw >= slope_aw;
+                if (fw_dir) {
+                    for (int64_t j = 0; j < n; ++j) d[j] = (j == js ? ai : 0.0) - t_i[j];
+                    gmax = 1.0;
+                } else {
+                    for (int64_t j = 0; j < n; ++j) d[j] = t_i[j] - (j == ja ? ai : 0.0);
+                    gmax = alpha / (1.0 - alpha);
+                }
+            }
+            double num = 0.0, dd = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                num -= d[j] * grad[j];
+                dd += d[j] * d[j];
+            }
+            const double den = P->w * dd;
+            if (!(num > 0.0)) gamma = 0.0;
+            else if (den == 0.0) gamma = gmax;
+            else gamma = num / den < gmax ? num / den : gmax;
+            drop = !fw_dir && gamma > 0.0 && gamma == gmax;
+            if (fw_dir) {
+                for (int64_t j = 0; j < n; ++j) t_i[j] = (1.0 - gamma) * t_i[j] + (j == js ? gamma * ai : 0.0);
+            } else if (pairwise) {
+                if (js != ja) {
+                    t_i[js] = t_i[js] + gamma * ai;
+                    t_i[ja] = t_i[ja] - gamma * ai;
+                }
+            } else {
+                for (int64_t j = 0; j < n; ++j) t_i[j] = (1.0 + gamma) * t_i[j] - (j == ja ? gamma * ai : 0.0);
+            }
+            if (drop) t_i[ja] = 0.0;
+        }
+        for (int64_t j = 0; j < n; ++j) r[j] += t_i[j] - old[j];
+        if (tr_j) tr_j[st] = (int32_t)js;
+        if (tr_away) tr_away[st] = (int32_t)(fw_dir ? -1 - ja : ja);
+        if (tr_gamma) tr_gamma[st] = gamma;
+        if (tr_margin) tr_margin[st] = margin;
+        if (tr_near) {
+            int cnt = 0;
+            for (int q = 0; q < 4; ++q) tr_near[st * 4 + q] = -1;
+            for (int64_t j = 0; j < n && cnt < 4; ++j)
+                if (grad[j] - grad[js] <= near_tol) tr_near[st * 4 + cnt++] = (int32_t)j;
+        }
+        if (tr_amargin || tr_anear) {
+            double second = -INFINITY;
+            int cnt = 0;
+            if (tr_anear) for (int q = 0; q < 4; ++q) tr_anear[st * 4 + q] = -1;
+            for (int64_t j = 0; j < n; ++j) {
+                if (!(old[j] > 0.0)) continue;
+                if (j != ja && grad[j] > second) second = grad[j];
+                if (tr_anear && ja >= 0 && grad[ja] - grad[j] <= near_tol && cnt < 4) tr_anear[st * 4 + cnt++] = (int32_t)j;
+            }
+            if (tr_amargin) tr_amargin[st] = (ja >= 0 && second > -INFINITY) ? grad[ja] - second : INFINITY;
+        }
+        *k += 1;
+    }
+    free(grad); free(d); free(old);
+    return 0;
+}
+
 /* Full Frank-Wolfe iteration (Alg. A.1, App. A): LMO on every block, then
  * one step on the whole plan.  ELS per eq. AppenEq:SemiRelaxedFWStep in the
  * penalty-weight form, with D = T - S:
