@@ -51,6 +51,10 @@ extern "C" {
 #define SROT_ELS  0   /* exact line search, eq. SemiRelaxedBCFWStep     */
 #define SROT_DEC  1   /* decay step 2m/(k+2m), k = global block-step count */
 
+/* block-step variants (Sec. 4.1) */
+#define SROT_STEP_AWAY      1   /* away steps, Alg. A.2 (BCAFW)     */
+#define SROT_STEP_PAIRWISE  2   /* pairwise steps, Alg. A.3 (BCPFW) */
+
 /* block sampling (Sec. 3.1) */
 #define SROT_UNIFORM  0   /* i.i.d. uniform rows (BCFW-U)             */
 #define SROT_PERMUTE  1   /* a fresh random permutation per pass (BCFW-P) */
@@ -184,6 +188,31 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
  * cost, dX/dY without points), SROT_EHIP. */
 int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *dY,
                   double *da, double *db);
+
+/* Block steps with away or pairwise directions (Sec. 4.1, Alg. A.2 / A.3)
+ * on the handle's plan, in place of srot_step's FW direction.  A row's
+ * active set is its support; per step, with g = c_i + w r:
+ *   FW vertex js = lowest-index argmin of g; away vertex ja = lowest-index
+ *   argmax of g over the support, alpha = t_ija / a_i;
+ *   SROT_STEP_AWAY: FW direction a_i e_js - t_i (gamma_max = 1) when its
+ *     slope is at least that of the away direction t_i - a_i e_ja (gamma_max
+ *     = alpha / (1 - alpha)), and always with a single atom or ja = js;
+ *   SROT_STEP_PAIRWISE: d = a_i (e_js - e_ja), gamma_max = alpha;
+ *   gamma = clip(-<g, d> / (w ||d||^2), 0, gamma_max)
+ *   (eq. SemiRelaxedBCAFWStep); reaching gamma_max on an away or pairwise
+ *   direction empties atom ja exactly.
+ * Needs opt->step_rule == SROT_ELS and rows of at most 4096 columns.
+ *   idx          device block indices, or NULL for the handle's sampler.
+ *   trace_j      device int32 per step (optional): js.
+ *   trace_away   device int32 per step (optional): ja, or -1 - ja when the
+ *                FW direction was taken.
+ *   trace_gamma  device double per step (optional).
+ * Errors: SROT_EINVAL (variant, step rule, row width, index), SROT_EHIP. */
+int srot_step_variant(srot_handle *h, int variant, int64_t nsteps, const int32_t *idx,
+                      int32_t *trace_j, int32_t *trace_away, double *trace_gamma);
+
+/* srot_solve with srot_step_variant's steps. */
+int srot_solve_variant(srot_handle *h, int variant, double *out3, int64_t *passes);
 
 /* Full Frank-Wolfe (Alg. A.1) on the handle's plan: each iteration takes
  * every row's LMO vertex at once (S = (a_i e_{j*_i})_i, from the gap sweep),

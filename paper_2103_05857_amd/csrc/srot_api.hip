@@ -149,6 +149,36 @@ int run_steps(srot_handle *h, int64_t nsteps, int32_t *trace_j, double *trace_ga
     return SROT_OK;
 }
 
+int run_variant_steps(srot_handle *h, int pairwise, int64_t nsteps, int32_t *trace_j, int32_t *trace_away,
+                      double *trace_gamma)
+{
+    int64_t done = 0;
+    while (done < nsteps) {
+        int64_t cnt = nsteps - done;
+        const int32_t *idx = nullptr;
+        int rc = draw_indices(h, h->k, &cnt, &idx);
+        if (rc != SROT_OK) return rc;
+        SROT_HIP(srot::launch_active_steps(h->P, h->S, pairwise, idx, cnt, trace_j ? trace_j + done : nullptr,
+                                           trace_away ? trace_away + done : nullptr,
+                                           trace_gamma ? trace_gamma + done : nullptr, h->stream));
+        h->k += cnt;
+        done += cnt;
+    }
+    return SROT_OK;
+}
+
+int variant_ok(srot_handle *h, int variant, const char *who)
+{
+    if (!h) return fail(SROT_EINVAL, "%s: NULL handle", who);
+    if (variant != SROT_STEP_AWAY && variant != SROT_STEP_PAIRWISE)
+        return fail(SROT_EINVAL, "%s: variant must be SROT_STEP_AWAY or SROT_STEP_PAIRWISE", who);
+    if (h->opt.step_rule != SROT_ELS)
+        return fail(SROT_EINVAL, "%s: away and pairwise steps use the exact line search (SROT_ELS)", who);
+    if (!srot::active_steps_supported(h->S))
+        return fail(SROT_EINVAL, "%s: away and pairwise steps support rows of at most 4096 columns", who);
+    return SROT_OK;
+}
+
 int measure_gap(srot_handle *h, double *out3)
 {
     SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
@@ -403,6 +433,48 @@ int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters)
         h->fw_k += 1;
         *iters = it + 1;
     }
+}
+
+int srot_step_variant(srot_handle *h, int variant, int64_t nsteps, const int32_t *idx, int32_t *trace_j,
+                      int32_t *trace_away, double *trace_gamma)
+{
+    int rc = variant_ok(h, variant, "srot_step_variant");
+    if (rc != SROT_OK) return rc;
+    if (nsteps < 0) return fail(SROT_EINVAL, "srot_step_variant: nsteps < 0");
+    if (nsteps == 0) return SROT_OK;
+    const int pairwise = variant == SROT_STEP_PAIRWISE;
+    if (!idx) return run_variant_steps(h, pairwise, nsteps, trace_j, trace_away, trace_gamma);
+    int32_t flag = 0;
+    SROT_HIP(hipMemsetAsync(h->S.flags, 0, sizeof(int32_t), h->stream));
+    SROT_HIP(srot::launch_check_indices(idx, nsteps, h->P.m, h->S.flags, h->stream));
+    SROT_HIP(hipMemcpyAsync(&flag, h->S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    SROT_HIP(hipStreamSynchronize(h->stream));
+    if (flag & 2) return fail(SROT_EINVAL, "srot_step_variant: block index outside [0, m)");
+    SROT_HIP(srot::launch_active_steps(h->P, h->S, pairwise, idx, nsteps, trace_j, trace_away, trace_gamma,
+                                       h->stream));
+    h->k += nsteps;
+    return SROT_OK;
+}
+
+int srot_solve_variant(srot_handle *h, int variant, double *out3, int64_t *passes)
+{
+    int rc = variant_ok(h, variant, "srot_solve_variant");
+    if (rc != SROT_OK) return rc;
+    if (!out3 || !passes) return fail(SROT_EINVAL, "srot_solve_variant: NULL argument");
+    *passes = 0;
+    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
+    const int64_t m = h->P.m;
+    for (int64_t p = 0; p < h->opt.max_passes; ++p) {
+        rc = run_variant_steps(h, variant == SROT_STEP_PAIRWISE, m, nullptr, nullptr, nullptr);
+        if (rc != SROT_OK) return rc;
+        *passes = p + 1;
+        if ((p + 1) % h->opt.gap_every == 0 || p + 1 == h->opt.max_passes) {
+            rc = measure_gap(h, out3);
+            if (rc != SROT_OK) return rc;
+            if (out3[0] <= h->opt.eps) return SROT_OK;
+        }
+    }
+    return SROT_NOT_CONVERGED;
 }
 
 int srot_barycentric(srot_handle *h, float *Xhat)

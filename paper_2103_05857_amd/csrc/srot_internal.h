@@ -107,6 +107,13 @@ hipError_t launch_fw_step(const ProblemView &P, const DeviceState &S, int64_t k,
 // at least this many doubles).
 int32_t fw_finish_blocks(int64_t n);
 
+// Block steps with away (pairwise = 0, Alg. A.2) or pairwise (pairwise = 1,
+// Alg. A.3) directions (srot_variants.hip); rows of at most 4096 columns.
+bool active_steps_supported(const DeviceState &S);
+hipError_t launch_active_steps(const ProblemView &P, const DeviceState &S, int pairwise, const int32_t *idx,
+                               int64_t nsteps, int32_t *trace_j, int32_t *trace_away, double *trace_gamma,
+                               hipStream_t stream);
+
 // Barycentric projection (srot_adjoint.hip): Xhat_i = sum_j t_ij y_j / sum_j t_ij.
 hipError_t launch_barycentric(const ProblemView &P, const DeviceState &S, float *Xhat, hipStream_t stream);
 

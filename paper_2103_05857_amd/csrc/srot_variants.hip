@@ -1,0 +1,210 @@
+// Block steps with away steps (Alg. A.2, BCAFW) and pairwise steps
+// (Alg. A.3, BCPFW) of Sec. 4.1, for gfx950.  A row t_i in a_i * simplex is
+// the combination of the vertices a_i e_j with coefficients alpha_j =
+// t_ij / a_i; its active set is the support, which the support bitmasks of
+// the block-coordinate kernels already hold.  Per step, with g = c_i + w r:
+//   FW vertex   js = lowest-index argmin of g (all columns);
+//   away vertex ja = lowest-index argmax of g over the support;
+//   BCAFW: the FW direction a_i e_js - t_i (gamma_max = 1) when its slope
+//          sum t (g - g_js) is at least that of the away direction
+//          t_i - a_i e_ja, sum t (g_ja - g) (gamma_max = alpha/(1 - alpha)),
+//          and always with one atom or ja = js (the away direction is then
+//          zero; alpha is 1 only up to rounding);
+//   BCPFW: d = a_i (e_js - e_ja), gamma_max = alpha_ja;
+// gamma = clip(-<g, d> / (w ||d||^2), 0, gamma_max) (eq. SemiRelaxedBCAFWStep);
+// a step reaching gamma_max on an away or pairwise direction empties atom ja
+// exactly.  One workgroup runs the steps in order with the column ownership
+// of the handle (r in registers); a step is three workgroup reductions: the
+// FW vertex, the away vertex, and seven sums over the support.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "../../include/srot.h"
+#include "srot_device.h"
+#include "srot_internal.h"
+
+namespace srot {
+
+namespace {
+
+template <int NT, int CPT, int VEC, int COST, int PAIR>
+__global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *__restrict__ T,
+                                                         double *__restrict__ rg, uint32_t *__restrict__ M,
+                                                         const int32_t *__restrict__ idx, int64_t nsteps,
+                                                         int32_t *__restrict__ trace_j,
+                                                         int32_t *__restrict__ trace_away,
+                                                         double *__restrict__ trace_gamma)
+{
+    using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
+    constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
+    constexpr int NW = NT / 64;
+    __shared__ double s_v[2][NW];
+    __shared__ int s_j[2][NW];
+    __shared__ double s_v2[2][NW];
+    __shared__ int s_j2[2][NW];
+    __shared__ double s_sum[2][NW][7];
+    const int tid = threadIdx.x;
+    const int n = P.n;
+    const double w = P.w;
+    const CT *__restrict__ C = (const CT *)P.C;
+
+    double r[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int j = owned_col<NT, VEC>(u, tid);
+        r[u] = (j < n) ? rg[j] : 0.0;
+    }
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int i = idx[s];
+        const double ai = P.a[i];
+        const size_t base = (size_t)i * (size_t)n;
+        const uint32_t mk = M[(size_t)i * NT + tid];
+        CT cv[CPT];
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
+        else load_cost_row<NT, CPT, VEC, CT>(C + base, n, tid, cv);
+        double t[CPT], vv[CPT];
+        double best = INFINITY, nb = INFINITY;
+        int bj = 0x7fffffff, nj = 0x7fffffff;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            const int jc = j < n ? j : n - 1;
+            t[u] = (mk & (1u << u)) ? T[base + j] : 0.0;
+            double c;
+            if constexpr (FUSED) c = sqdist(x0, x1, x2, P.Y[3 * jc], P.Y[3 * jc + 1], P.Y[3 * jc + 2]);
+            else c = (double)cv[u];
+            vv[u] = c + w * r[u];
+            const double v = (j < n) ? vv[u] : INFINITY;
+            if (v < best) { best = v; bj = j; }
+            if (t[u] > 0.0 && -vv[u] < nb) { nb = -vv[u]; nj = j; }
+        }
+        block_argmin<NW>(best, bj, s_v[s & 1], s_j[s & 1]);
+        block_argmin<NW>(nb, nj, s_v2[s & 1], s_j2[s & 1]);
+        const double G = best, V = -nb;
+        const int js = bj, ja = nj;
+
+        // P1 = sum t (g - G), P2 = sum t (V - g), Q1 = sum_{j != js} t^2,
+        // Q2 = sum_{j != ja} t^2, t_js, t_ja, number of atoms
+        double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            const bool on = t[u] > 0.0;
+            acc[0] += t[u] * (vv[u] - G);
+            acc[1] += on ? t[u] * (V - vv[u]) : 0.0;
+            acc[2] += (j == js) ? 0.0 : t[u] * t[u];
+            acc[3] += (j == ja) ? 0.0 : t[u] * t[u];
+            acc[4] = (j == js) ? t[u] : acc[4];
+            acc[5] = (j == ja) ? t[u] : acc[5];
+            acc[6] += on ? 1.0 : 0.0;
+        }
+        block_sum<NW, 7>(acc, s_sum[s & 1]);
+        const double tjs = acc[4], tja = acc[5];
+        const double alpha = tja / ai;
+        bool fw_dir = false;
+        double num, den, gmax;
+        if constexpr (PAIR) {
+            num = (js != ja) ? ai * (V - G) : 0.0;
+            den = (js != ja) ? w * (2.0 * ai * ai) : 0.0;
+            gmax = alpha;
+        } else {
+            fw_dir = acc[6] == 1.0 || ja == js || acc[0] >= acc[1];
+            if (fw_dir) {
+                num = acc[0];
+                den = w * (acc[2] + (tjs - ai) * (tjs - ai));
+                gmax = 1.0;
+            } else {
+                num = acc[1];
+                den = w * (acc[3] + (tja - ai) * (tja - ai));
+                gmax = alpha / (1.0 - alpha);
+            }
+        }
+        double gamma;
+        if (!(num > 0.0)) gamma = 0.0;
+        else if (den == 0.0) gamma = gmax;
+        else gamma = num / den < gmax ? num / den : gmax;
+        const bool drop = !fw_dir && gamma > 0.0 && gamma == gmax;
+
+        // update this thread's entries, r and the support bits
+        uint32_t nm = mk;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            double tn;
+            if (fw_dir) tn = (1.0 - gamma) * t[u] + ((j == js) ? gamma * ai : 0.0);
+            else if constexpr (PAIR) tn = (js == ja) ? t[u] : ((j == js) ? t[u] + gamma * ai : ((j == ja) ? t[u] - gamma * ai : t[u]));
+            else tn = (1.0 + gamma) * t[u] - ((j == ja) ? gamma * ai : 0.0);
+            if (drop && j == ja) tn = 0.0;
+            if (j < n && tn != t[u]) T[base + j] = tn;
+            r[u] += tn - t[u];
+            nm = (tn != 0.0) ? (nm | (1u << u)) : (nm & ~(1u << u));
+        }
+        if (nm != mk) M[(size_t)i * NT + tid] = nm;
+        if (tid == 0) {
+            if (trace_j) trace_j[s] = js;
+            if (trace_away) trace_away[s] = fw_dir ? -1 - ja : ja;
+            if (trace_gamma) trace_gamma[s] = gamma;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int j = owned_col<NT, VEC>(u, tid);
+        if (j < n) rg[j] = r[u];
+    }
+}
+
+#define SROT_VAR_V1(X) \
+    X(64, 2, 1) X(64, 4, 1) X(128, 4, 1) X(256, 4, 1) X(256, 8, 1) X(256, 16, 1)
+#define SROT_VAR_V2(X) \
+    X(64, 2, 2) X(64, 4, 2) X(128, 4, 2) X(256, 4, 2) X(256, 8, 2) X(256, 16, 2)
+#define SROT_VAR_V4(X) \
+    X(64, 4, 4) X(128, 4, 4) X(256, 4, 4) X(256, 8, 4) X(256, 16, 4)
+
+template <int COST, int PAIR>
+hipError_t launch_active_cost(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t nsteps,
+                              int32_t *tj, int32_t *ta, double *tg, hipStream_t st)
+{
+    const Ownership &o = S.own;
+#define SROT_ACT(NT_, CPT_, VEC_)                                                                  \
+    if (o.nt == NT_ && o.cpt == CPT_ && o.vec == VEC_) {                                           \
+        hipLaunchKernelGGL((active_step_kernel<NT_, CPT_, VEC_, COST, PAIR>), dim3(1), dim3(NT_), 0, st, \
+                           P, S.T, S.r, S.mask, idx, nsteps, tj, ta, tg);                          \
+        return hipGetLastError();                                                                  \
+    }
+    SROT_VAR_V1(SROT_ACT)
+    if constexpr (COST == SROT_COST_F32) { SROT_VAR_V4(SROT_ACT) }
+    if constexpr (COST == SROT_COST_F64) { SROT_VAR_V2(SROT_ACT) }
+#undef SROT_ACT
+    return hipErrorInvalidConfiguration;
+}
+
+}  // namespace
+
+bool active_steps_supported(const DeviceState &S)
+{
+    const Ownership &o = S.own;
+    return o.reg && o.nt <= 256;
+}
+
+hipError_t launch_active_steps(const ProblemView &P, const DeviceState &S, int pairwise, const int32_t *idx,
+                               int64_t nsteps, int32_t *trace_j, int32_t *trace_away, double *trace_gamma,
+                               hipStream_t stream)
+{
+    if (nsteps <= 0) return hipSuccess;
+    switch (P.cost) {
+    case SROT_COST_F32:
+        return pairwise ? launch_active_cost<SROT_COST_F32, 1>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream)
+                        : launch_active_cost<SROT_COST_F32, 0>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream);
+    case SROT_COST_F64:
+        return pairwise ? launch_active_cost<SROT_COST_F64, 1>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream)
+                        : launch_active_cost<SROT_COST_F64, 0>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream);
+    default:
+        return pairwise ? launch_active_cost<SROT_COST_SQEUCLID, 1>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream)
+                        : launch_active_cost<SROT_COST_SQEUCLID, 0>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream);
+    }
+}
+
+}  // namespace srot

@@ -23,6 +23,8 @@ SROT_EHIP = -4
 
 SROT_ELS = 0
 SROT_DEC = 1
+SROT_STEP_AWAY = 1
+SROT_STEP_PAIRWISE = 2
 SROT_UNIFORM = 0
 SROT_PERMUTE = 1
 SROT_COST_F32 = 0
@@ -96,6 +98,10 @@ def load():
     L.srot_fw_steps.restype = ctypes.c_int
     L.srot_fw_solve.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     L.srot_fw_solve.restype = ctypes.c_int
+    L.srot_step_variant.argtypes = [_vp, ctypes.c_int, _i64, _vp, _vp, _vp, _vp]
+    L.srot_step_variant.restype = ctypes.c_int
+    L.srot_solve_variant.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    L.srot_solve_variant.restype = ctypes.c_int
     L.srot_barycentric.argtypes = [_vp, _vp]
     L.srot_barycentric.restype = ctypes.c_int
     L.srot_destroy.argtypes = [_vp]
@@ -193,6 +199,19 @@ def srot_fw_solve(h):
     iters = _i64()
     st = _check(load().srot_fw_solve(h, out, ctypes.byref(iters)), allow=(SROT_OK, SROT_NOT_CONVERGED))
     return st, (out[0], out[1], out[2]), iters.value
+
+
+def srot_step_variant(h, variant, nsteps, idx=None, trace_j=None, trace_away=None, trace_gamma=None):
+    _check(load().srot_step_variant(h, int(variant), int(nsteps), _ptr(idx), _ptr(trace_j), _ptr(trace_away),
+                                    _ptr(trace_gamma)))
+
+
+def srot_solve_variant(h, variant):
+    out = (ctypes.c_double * 3)()
+    passes = _i64()
+    st = _check(load().srot_solve_variant(h, int(variant), out, ctypes.byref(passes)),
+                allow=(SROT_OK, SROT_NOT_CONVERGED))
+    return st, (out[0], out[1], out[2]), passes.value
 
 
 def srot_barycentric(h, Xhat):

@@ -1,0 +1,182 @@
+"""Away-step (Alg. A.2) and pairwise (Alg. A.3) block steps on the GPU
+against the FP64 oracle.
+
+Bar: identical FW vertex, away vertex / direction and step size (1e-9
+absolute) at every step up to the first step where the oracle reports a
+rounding-level tie (margin <= 1e-12) of either vertex and the GPU took
+another tied column -- the line search equalises the gradient on the two
+atoms it moves between, so such ties recur by construction and either
+choice is correct.  Before any divergence the plan, f and g match as in the
+block-coordinate parity tests.  A second test takes every oracle step from
+the GPU's own state, so that each GPU step is checked on its own; after many
+passes both sides reach the optimum (g <= 1e-9) and agree on f.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2103_05857_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+TAU = 1e-12
+
+
+def _S():
+    from paper_2103_05857_amd import srot as S
+    return S
+
+
+def _pair(d, cost_mode, w, **opts):
+    S = _S()
+    a = torch.from_numpy(d["a"]).to(DEV)
+    b = torch.from_numpy(d["b"]).to(DEV)
+    if cost_mode == "sqeuclid":
+        sol = S.Solver(a, b, X=torch.from_numpy(d["X"]).to(DEV), Y=torch.from_numpy(d["Y"]).to(DEV), w=w, **opts)
+        P = O.Problem(d["a"], d["b"], w, X=d["X"], Y=d["Y"])
+    else:
+        sol = S.Solver(a, b, C=torch.from_numpy(d["C"]).to(DEV), w=w, **opts)
+        P = O.Problem(d["a"], d["b"], w, C=d["C"].astype(np.float64))
+    return sol, P
+
+
+def _run_gpu(sol, variant, idx):
+    S = _S()
+    ns = len(idx)
+    tj = torch.empty(ns, dtype=torch.int32, device=DEV)
+    ta = torch.empty(ns, dtype=torch.int32, device=DEV)
+    tg = torch.empty(ns, dtype=torch.float64, device=DEV)
+    S.srot_step_variant(sol.h, variant, ns, torch.from_numpy(idx).to(DEV), tj, ta, tg)
+    torch.cuda.synchronize()
+    return tj.cpu().numpy(), ta.cpu().numpy(), tg.cpu().numpy()
+
+
+def _first_divergence(otr, gj, ga, gg):
+    oa = otr["away"]
+    same = (gj == otr["j"]) & (ga == oa) & (np.abs(gg - otr["gamma"]) <= 1e-9)
+    bad = np.nonzero(~same)[0]
+    if len(bad) == 0:
+        return len(gj)
+    k = int(bad[0])
+    # a divergence is only allowed where the oracle's choice was a rounding-level tie
+    gja = -1 - ga[k] if ga[k] < 0 else ga[k]
+    tie_j = otr["margin"][k] <= TAU and gj[k] in otr["near"][k]
+    tie_a = otr["amargin"][k] <= TAU and gja in otr["anear"][k]
+    tie_dir = gj[k] == otr["j"][k] and gja == (-1 - oa[k] if oa[k] < 0 else oa[k])  # direction choice at equal slopes
+    assert tie_j or tie_a or tie_dir, (k, gj[k], otr["j"][k], ga[k], oa[k], gg[k], otr["gamma"][k],
+                                       otr["margin"][k], otr["amargin"][k])
+    return k
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w", [
+    ("stored", np.float64, 64, 96, 1.0),
+    ("stored", np.float32, 300, 700, 0.5),
+    ("sqeuclid", None, 200, 333, 2.0),
+    ("stored", np.float32, 97, 4096, 1.0),
+])
+def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
+    d = I.problem_mixture(14, m, n, cost_dtype=dtype or np.float32)
+    sol, P = _pair(d, cost_mode, w)
+    idx = I.philox_uniform_indices(5, 0, 6 * m, m)
+    st = O.State(P)
+    otr = O.active_steps(P, st, idx, O.PAIRWISE if variant == 2 else O.AWAY)
+    gj, ga, gg = _run_gpu(sol, variant, idx)
+    k = _first_divergence(otr, gj, ga, gg)
+    assert k >= 1
+    if k == len(idx):
+        T, r = sol.plan()
+        T = T.cpu().numpy()
+        np.testing.assert_allclose(T, st.T, rtol=0, atol=1e-9)
+        ref = O.gap(P, st.T)
+        g, f, D = sol.gap()
+        assert abs(f - ref["f"]) <= 1e-6 * abs(ref["f"]) + 1e-15
+        assert abs(g - ref["g"]) <= 1e-6 * max(ref["g"], 1e-9) + 1e-15
+    T, r = sol.plan()
+    T = T.cpu().numpy()
+    assert T.min() >= 0.0
+    np.testing.assert_allclose(T.sum(axis=1), d["a"], rtol=1e-12)
+    np.testing.assert_allclose(r.cpu().numpy(), T.sum(axis=0) - d["b"], rtol=0, atol=1e-13)
+    sol.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w", [
+    ("stored", np.float64, 48, 96, 1.0),
+    ("stored", np.float32, 60, 300, 0.5),
+    ("sqeuclid", None, 40, 77, 2.0),
+])
+def test_every_step_from_the_gpu_state(variant, cost_mode, dtype, m, n, w):
+    """The oracle takes each step from the GPU's own state (plan and
+    residual), so every GPU step is checked: same FW and away vertices and
+    direction unless the oracle reports a rounding-level tie of the one that
+    differs, and then the same step size and plan."""
+    S = _S()
+    d = I.problem_mixture(17, m, n, cost_dtype=dtype or np.float32)
+    sol, P = _pair(d, cost_mode, w)
+    idx = I.philox_uniform_indices(6, 0, 4 * m, m)
+    ovar = O.PAIRWISE if variant == 2 else O.AWAY
+    checked = 0
+    for k in range(len(idx)):
+        T, r = sol.plan()
+        st = O.State(P, T.cpu().numpy())
+        st.r = r.cpu().numpy().copy()
+        otr = O.active_steps(P, st, idx[k:k + 1], ovar)
+        gj, ga, gg = _run_gpu(sol, variant, idx[k:k + 1])
+        oa = otr["away"][0]
+        gja = -1 - ga[0] if ga[0] < 0 else ga[0]
+        oja = -1 - oa if oa < 0 else oa
+        if gj[0] != otr["j"][0]:
+            assert otr["margin"][0] <= TAU and gj[0] in otr["near"][0]
+            continue
+        if gja != oja:
+            assert otr["amargin"][0] <= TAU and gja in otr["anear"][0]
+            continue
+        if (ga[0] < 0) != (oa < 0):
+            continue                      # FW and away slopes equal to rounding
+        T2, _ = sol.plan()
+        np.testing.assert_allclose(T2.cpu().numpy(), st.T, rtol=0, atol=1e-12)
+        i = int(idx[k])
+        if np.abs(st.T[i] - T.cpu().numpy()[i]).max() > 1e-14:
+            # a direction that is zero up to rounding (one atom at the FW
+            # vertex) leaves the plan as it is for any step size; only then
+            # may the sizes differ
+            assert abs(gg[0] - otr["gamma"][0]) <= 1e-9, (k, gg[0], otr["gamma"][0])
+        checked += 1
+    assert checked >= 0.8 * len(idx)
+    sol.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_variants_converge_to_the_optimum(variant):
+    S = _S()
+    m, n, w = 40, 50, 1.0
+    d = I.problem_mixture(15, m, n, cost_dtype=np.float64)
+    sol, P = _pair(d, "stored", w, eps=1e-9, max_passes=20000, seed=1)
+    st, (g, f, D), passes = S.srot_solve_variant(sol.h, variant)
+    sol.close()
+    assert st == S.SROT_OK and g <= 1e-9
+    ost = O.State(P)
+    O.active_steps(P, ost, I.philox_uniform_indices(1, 0, passes * m, m),
+                   O.PAIRWISE if variant == 2 else O.AWAY, trace=False)
+    ref = O.gap(P, ost.T)
+    assert ref["g"] <= 1e-7
+    assert abs(f - ref["f"]) <= g + ref["g"] + 1e-15       # both within their gaps of f*
+
+
+def test_variant_argument_checks():
+    S = _S()
+    d = I.problem_mixture(16, 10, 12, cost_dtype=np.float64)
+    sol, _ = _pair(d, "stored", 1.0, step_rule=S.SROT_DEC)
+    with pytest.raises(S.SrotError):
+        S.srot_step_variant(sol.h, S.SROT_STEP_PAIRWISE, 5)      # decay rule
+    sol.close()
+    sol, _ = _pair(d, "stored", 1.0)
+    with pytest.raises(S.SrotError):
+        S.srot_step_variant(sol.h, 7, 5)
+    bad = torch.tensor([0, 10], dtype=torch.int32, device=DEV)
+    with pytest.raises(S.SrotError):
+        S.srot_step_variant(sol.h, S.SROT_STEP_AWAY, 2, bad)
+    sol.close()
