@@ -59,8 +59,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solves")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--sections", type=str, default="sweep,batched,diff,fused",
-                    help="extra workloads after the stored-cost one: sweep, batched, diff, fused")
+    ap.add_argument("--sections", type=str, default="sweep,fw,variants,batched,diff,fused",
+                    help="extra workloads after the stored-cost one: sweep, fw, variants, batched, diff, fused")
     ap.add_argument("--sweep-n", type=int, default=16384)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=64,
@@ -184,6 +184,10 @@ def main():
     sections = [x for x in args.sections.split(",") if x]
     if "sweep" in sections:
         out["gap_sweep_1GiB"] = bench_sweep(args)
+    if "fw" in sections:
+        out["full_fw"] = bench_fw(args, C, a, b)
+    if "variants" in sections:
+        out["variants_time_to_gap_1e-6"] = bench_variants(args, C, a, b)
     if "batched" in sections:
         out["batched"] = bench_batched(args)
     if "diff" in sections:
@@ -241,6 +245,64 @@ def bench_sweep(args):
             "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS,
             "traffic": counter_traffic("srot::gap_sweep_kernel<0, 4, 2>", SWEEP_PROFILE, grid=1024 * 256)}
+
+
+def bench_fw(args, C, a, b):
+    """Full Frank-Wolfe (Alg. A.1) on the stored-cost workload (w = 1): the
+    time of one iteration (gap sweep, vertex column sums, line search,
+    update) from HIP events around srot_fw_steps, and its stream rate."""
+    import torch
+    from paper_2103_05857_amd import srot as S
+    m, n = C.shape
+    sol = S.Solver(a, b, C=C, w=1.0, seed=0)
+    S.srot_fw_steps(sol.h, 5)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    iters = 100
+    e0.record(stream)
+    S.srot_fw_steps(sol.h, iters)
+    e1.record(stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / iters
+    g, f, D = sol.gap()
+    T, _ = sol.plan()
+    nnz = int((T > 0).sum().item())
+    del T
+    sol.close()
+    # per iteration: the cost streamed once (4mn), the plan's support read and
+    # written (24 B per nonzero), the vertex indices, r, b and s
+    byts = 4.0 * m * n + 24.0 * nnz + 4.0 * m + 8.0 * 4 * n
+    return {"workload": f"full FW, m=n={m}, FP32 stored cost, w=1, ELS", "us_per_iteration": t * 1e6,
+            "bytes_per_iteration": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": byts / t / 1e9 / HBM_PEAK_GBS, "gap_after_105_iterations": g}
+
+
+def bench_variants(args, C, a, b):
+    """Time to gap 1e-6 from the initial plan on the stored-cost workload
+    (w = 1, uniform sampling, gap every pass): plain BCFW (Alg. 1) against
+    the away-step (Alg. A.2) and pairwise (Alg. A.3) block steps and full FW
+    (Alg. A.1, gap at every iteration; "passes" counts its iterations)."""
+    import torch
+    from paper_2103_05857_amd import srot as S
+    out = {}
+    for name, variant in (("bcfw", None), ("away", S.SROT_STEP_AWAY), ("pairwise", S.SROT_STEP_PAIRWISE),
+                          ("full_fw", "fw")):
+        sol = S.Solver(a, b, C=C, w=1.0, seed=0, eps=1e-6, max_passes=2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if variant is None:
+            st, (g, f, D), passes = sol.solve()
+        elif variant == "fw":
+            st, (g, f, D), passes = S.srot_fw_solve(sol.h)    # passes = FW iterations
+        else:
+            st, (g, f, D), passes = S.srot_solve_variant(sol.h, variant)
+        torch.cuda.synchronize()
+        out[name] = dict(seconds=time.perf_counter() - t0, passes=passes, gap=g, f=f,
+                         converged=(st == S.SROT_OK))
+        sol.close()
+    return out
 
 
 def bench_batched(args):
