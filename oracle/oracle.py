@@ -62,6 +62,13 @@ def _load():
     lib.or_active_steps.restype = ctypes.c_int
     lib.or_fw_iteration.argtypes = [P, _dp, ctypes.c_int64, ctypes.c_int, _dp]
     lib.or_fw_iteration.restype = ctypes.c_double
+    lib.or_row_gap.argtypes = [P, _dp, _dp, ctypes.c_int64]
+    lib.or_row_gap.restype = ctypes.c_double
+    lib.or_ga_draw.argtypes = [ctypes.c_int64, _dp, ctypes.c_double, _dp]
+    lib.or_ga_draw.restype = ctypes.c_int64
+    lib.or_ga_steps.argtypes = [P, _dp, _dp, _i64p, ctypes.c_int, ctypes.c_int64, _dp, _dp, _i32p, _dp,
+                                _i32p, _dp, _dp, _i32p, _dp, ctypes.c_double]
+    lib.or_ga_refresh.argtypes = [P, _dp, _dp]
     _lib = lib
     return lib
 
@@ -285,3 +292,81 @@ def barycentric(T, X, Y):
         if den > 0.0:
             out[i] = (T[i][:, None] * Y).sum(axis=0) / den
     return out
+
+
+# BCFW with gap-adaptive sampling (Alg. A.4, Sec. 4.2.1).  Every stored block
+# gap starts at a large constant; 2^300 is exact under addition of up to 2^53
+# copies and absorbs any real block gap below 2^246, so blocks not yet
+# visited are drawn (uniformly) before any visited one.
+GA_INIT = 2.0 ** 300
+
+
+def row_gap(P, T, r, i):
+    """Gap of block i (eq. AppenEq:Gi) at plan T with residual r."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    return _load().or_row_gap(P.ref, _ptr(T, ctypes.c_double), _ptr(r, ctypes.c_double), int(i))
+
+
+def ga_draw(W, u):
+    """Block drawn from the stored gaps W with uniform u (see or_ga_draw);
+    returns (i, margin relative to the sum of W)."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    mg = ctypes.c_double()
+    i = _load().or_ga_draw(W.shape[0], _ptr(W, ctypes.c_double), float(u), ctypes.byref(mg))
+    return int(i), mg.value
+
+
+def ga_weights(P, init=GA_INIT):
+    return np.full(P.m, float(init), dtype=np.float64)
+
+
+def ga_refresh(P, T):
+    """Global update of Alg. A.4: every block's gap at T (clamped at 0)."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    W = np.empty(P.m, dtype=np.float64)
+    _load().or_ga_refresh(P.ref, _ptr(T, ctypes.c_double), _ptr(W, ctypes.c_double))
+    return W
+
+
+def ga_steps(P, state, W, u, rule=ELS, trace=True, near_tol=1e-12):
+    """len(u) iterations of Alg. A.4 in place on state and on the stored
+    gaps W (float64, length m): draw, BCFW block step, store the drawn
+    block's new gap.  Returns dict(i, umargin, j, gamma, margin, near, g)
+    when trace is set."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert W.dtype == np.float64 and W.flags.c_contiguous and W.shape == (P.m,)
+    ns = u.shape[0]
+    out = None
+    if trace:
+        out = dict(i=np.empty(ns, np.int32), umargin=np.empty(ns), j=np.empty(ns, np.int32),
+                   gamma=np.empty(ns), margin=np.empty(ns), near=np.empty((ns, 4), np.int32),
+                   g=np.empty(ns))
+    g = (lambda key, ct: _ptr(out[key], ct)) if trace else (lambda key, ct: None)
+    k = ctypes.c_int64(state.k)
+    _load().or_ga_steps(P.ref, _ptr(state.T, ctypes.c_double), _ptr(state.r, ctypes.c_double),
+                        ctypes.byref(k), int(rule), ns, _ptr(u, ctypes.c_double), _ptr(W, ctypes.c_double),
+                        g("i", ctypes.c_int32), g("umargin", ctypes.c_double), g("j", ctypes.c_int32),
+                        g("gamma", ctypes.c_double), g("margin", ctypes.c_double), g("near", ctypes.c_int32),
+                        g("g", ctypes.c_double), float(near_tol))
+    state.k = k.value
+    return out
+
+
+def solve_ga(P, u_source, period=1, init=GA_INIT, rule=ELS, eps=0.0, max_passes=1):
+    """Outer iterations of Alg. A.4: passes of m inner iterations; after each
+    pass the gap is measured (stop at g <= eps, Sec. 3.1), and after every
+    `period` passes all stored block gaps are recomputed (global update).
+    u_source(p) returns the m uniforms of pass p.  Returns (state, W, hist)."""
+    st = State(P)
+    W = ga_weights(P, init)
+    hist = []
+    for p in range(max_passes):
+        ga_steps(P, st, W, u_source(p), rule=rule, trace=False)
+        gp = gap(P, st.T)
+        hist.append(dict(passes=p + 1, g=gp["g"], f=gp["f"], D=gp["D"]))
+        if gp["g"] <= eps:
+            break
+        if (p + 1) % period == 0:
+            W[:] = ga_refresh(P, st.T)
+    return st, W, hist

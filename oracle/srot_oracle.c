@@ -433,3 +433,102 @@ double or_fw_iteration(const or_problem *P, double *T, int64_t k, int rule,
     free(r); free(grad); free(S);
     return num;
 }
+
+/* -------------------------------------------------------------------------
+ * BCFW with gap-adaptive sampling (BCFW-GA, Alg. A.4, Sec. 4.2.1).
+ * ---------------------------------------------------------------------- */
+
+/* Gap of one block (eq. AppenEq:Gi) at plan T with residual r:
+ *     g_i = <t_i - s_i, c_i> + w <t_i - s_i, r>,
+ * s_i = a_i e_j* the block's LMO vertex at r.  The sum over the blocks is the
+ * linearization gap g(T) (Thm 2). */
+double or_row_gap(const or_problem *P, const double *T, const double *r, int64_t i)
+{
+    const int64_t n = P->n;
+    double *grad = (double *)malloc(sizeof(double) * (size_t)n);
+    or_block_gradient(P, r, i, grad);
+    const int64_t js = or_lmo(n, grad, NULL);
+    free(grad);
+    double lin = 0.0, pen = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double d = T[i * n + j] - ((j == js) ? P->a[i] : 0.0);
+        lin += d * or_cost(P, i, j);
+        pen += d * r[j];
+    }
+    return lin + P->w * pen;
+}
+
+/* Block draw of Alg. A.4: block i with probability W_i / sum_q W_q, by
+ * inversion.  The running sums S_i = W_0 + ... + W_i are formed in row
+ * order, x = u * S_{m-1} with u in [0, 1), and i is the first block with
+ * S_i > x; a block of zero weight is therefore never drawn.  Should
+ * rounding leave x at or above the full sum, x is replaced by the largest
+ * double below it.  When every weight is zero, i = floor(u m).
+ * *margin receives the distance from x to the nearer end of the chosen
+ * block's interval [S_{i-1}, S_i), relative to the full sum (+inf when
+ * every weight is zero). */
+int64_t or_ga_draw(int64_t m, const double *W, double u, double *margin)
+{
+    double total = 0.0;
+    for (int64_t q = 0; q < m; ++q) total += W[q];
+    if (!(total > 0.0)) {
+        int64_t i = (int64_t)(u * (double)m);
+        if (margin) *margin = INFINITY;
+        return i < m ? i : m - 1;
+    }
+    double x = u * total;
+    if (x >= total) x = nextafter(total, 0.0);
+    double lo = 0.0, run = 0.0;
+    for (int64_t q = 0; q < m; ++q) {
+        const double hi = run + W[q];
+        if (hi > x) {
+            const double d1 = x - lo, d2 = hi - x;
+            if (margin) *margin = (d1 < d2 ? d1 : d2) / total;
+            return q;
+        }
+        lo = hi;
+        run = hi;
+    }
+    if (margin) *margin = 0.0;   /* not reached: S_{m-1} = total > x */
+    return m - 1;
+}
+
+/* nsteps iterations of Alg. A.4 in place on (T, r, *k, W): draw a block
+ * from the stored gaps W (or_ga_draw with the given uniform u[s]), take
+ * the BCFW block step of Alg. 1 on it (or_bcfw_steps: LMO, step rule, block
+ * and marginal update), then store that block's gap at the new plan,
+ * clamped at 0 (the exact value is non-negative; the clamp only removes a
+ * rounding-level negative that would be no probability).  The global
+ * update of all stored gaps is or_ga_refresh, called by the driver of the
+ * outer iterations.  Traces (each optional): the drawn block, its draw
+ * margin, the vertex, the step, the LMO margin and near set (as
+ * or_bcfw_steps), and the stored gap. */
+void or_ga_steps(const or_problem *P, double *T, double *r, int64_t *k, int rule, int64_t nsteps,
+                 const double *u, double *W, int32_t *tr_i, double *tr_umargin, int32_t *tr_j,
+                 double *tr_gamma, double *tr_margin, int32_t *tr_near, double *tr_g, double near_tol)
+{
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double um;
+        const int32_t i = (int32_t)or_ga_draw(P->m, W, u[s], &um);
+        or_bcfw_steps(P, T, r, k, rule, 1, &i, tr_j ? tr_j + s : NULL, tr_gamma ? tr_gamma + s : NULL,
+                      tr_margin ? tr_margin + s : NULL, NULL, tr_near ? tr_near + 4 * s : NULL, near_tol);
+        const double g = or_row_gap(P, T, r, i);
+        W[i] = g > 0.0 ? g : 0.0;
+        if (tr_i) tr_i[s] = i;
+        if (tr_umargin) tr_umargin[s] = um;
+        if (tr_g) tr_g[s] = W[i];
+    }
+}
+
+/* Global update of Alg. A.4: every block's gap (eq. AppenEq:Gi) at plan T,
+ * with the residual recomputed from T, clamped at 0 as in or_ga_steps. */
+void or_ga_refresh(const or_problem *P, const double *T, double *W)
+{
+    double *r = (double *)malloc(sizeof(double) * (size_t)P->n);
+    or_residual(P, T, r);
+    for (int64_t i = 0; i < P->m; ++i) {
+        const double g = or_row_gap(P, T, r, i);
+        W[i] = g > 0.0 ? g : 0.0;
+    }
+    free(r);
+}

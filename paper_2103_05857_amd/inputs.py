@@ -19,6 +19,8 @@ Block-index streams (the uniform sampler's draws, counter-based):
       i_k = floor(x_k * m / 2^64) with x_k the k-th 64-bit output of
       Philox4x64-10 (key = (seed, 0)), numpy's counter convention: output k
       is lane k mod 4 of the block at counter 1 + floor(k / 4).
+  * philox_uniform_doubles(seed, k0, count)
+      u_k = floor(x_k / 2^11) * 2^-53 in [0, 1), same outputs x_k.
   * philox_permutation_indices(seed, p0, npasses, m)
       pass p visits the rows in the order of a stable ascending sort of the
       keys x_{p*m + t}, t = 0..m-1.
@@ -80,6 +82,11 @@ def philox_uniform_indices(seed: int, k0: int, count: int, m: int) -> np.ndarray
     t = lo * m
     u = hi * m + (t >> np.uint64(32))
     return (u >> np.uint64(32)).astype(np.int32)
+
+
+def philox_uniform_doubles(seed: int, k0: int, count: int) -> np.ndarray:
+    x = philox_raw(seed, k0, count)
+    return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
 def philox_permutation_indices(seed: int, p0: int, npasses: int, m: int) -> np.ndarray:
