@@ -214,6 +214,50 @@ int srot_step_variant(srot_handle *h, int variant, int64_t nsteps, const int32_t
 /* srot_solve with srot_step_variant's steps. */
 int srot_solve_variant(srot_handle *h, int variant, double *out3, int64_t *passes);
 
+/* Block-coordinate Frank-Wolfe with gap-adaptive sampling (BCFW-GA,
+ * Alg. A.4, Sec. 4.2.1).  The handle keeps a stored gap W_i per row (block);
+ * srot_init sets every W_i to SROT_GA_INIT.  An inner iteration draws row i
+ * with probability W_i / sum W by inversion of x = u sum W (a row of zero
+ * weight is never drawn; with every weight zero, i = floor(u m)), takes the
+ * BCFW block step of srot_step on it (opt->step_rule), and stores the row's
+ * gap at the new plan, g_i = <t_i - s_i, c_i + w r> (eq. AppenEq:Gi, >= 0).
+ * The global update recomputes every W_i at the current plan.
+ * Rows of at most 4096 columns and at most 16384 rows.
+ * The initial constant 2^300 is exact under addition and absorbs every real
+ * row gap, so rows not yet visited are drawn (uniformly) before any other. */
+#define SROT_GA_INIT 0x1p300
+
+/* Every stored row gap <- init (> 0 and finite, m * init finite). */
+int srot_ga_reset(srot_handle *h, double init);
+
+/* Global update: every stored row gap <- the gap sweep's g_i at the current
+ * plan (one sweep; enqueued, no synchronisation). */
+int srot_ga_refresh(srot_handle *h);
+
+/* Copies the m stored row gaps to W_out (device, m doubles); enqueued. */
+int srot_ga_weights(srot_handle *h, double *W_out);
+
+/* nsteps inner iterations (enqueued, no synchronisation).
+ *   u            device, nsteps uniforms in [0, 1) (others count as 0), or
+ *                NULL: u_s = floor(x / 2^11) 2^-53 with x the output k + s
+ *                of the handle's block-index stream (Philox4x64-10, key
+ *                (seed, 0)), k the global block-step counter.
+ *   trace_i      device int32 per step (optional): the drawn row.
+ *   trace_j      device int32 per step (optional): its LMO vertex.
+ *   trace_gamma  device double per step (optional): the step size.
+ *   trace_g      device double per step (optional): the stored row gap.
+ * Errors: SROT_EINVAL (NULL handle, nsteps < 0, problem too large), SROT_EHIP. */
+int srot_step_ga(srot_handle *h, int64_t nsteps, const double *u, int32_t *trace_i, int32_t *trace_j,
+                 double *trace_gamma, double *trace_g);
+
+/* Outer iterations of Alg. A.4 from the current plan: every stored gap set
+ * to init (init <= 0: SROT_GA_INIT), then passes of m inner iterations
+ * (u from the handle's stream); the gap is measured every opt->gap_every
+ * passes (stop at g <= opt->eps) and every `period` passes (>= 1) the
+ * global update runs (reusing that pass's sweep).  out3 (host) = {g, f, D};
+ * *passes (host).  Returns SROT_OK or SROT_NOT_CONVERGED. */
+int srot_solve_ga(srot_handle *h, double init, int64_t period, double *out3, int64_t *passes);
+
 /* Full Frank-Wolfe (Alg. A.1) on the handle's plan: each iteration takes
  * every row's LMO vertex at once (S = (a_i e_{j*_i})_i, from the gap sweep),
  * and moves T <- (1 - gamma) T + gamma S with the decay step 2/(k+2) (k =

@@ -53,7 +53,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, resume, Y4, adj, total;
+    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, resume, Y4, adj, ga_w, total;
     int64_t idx_cap;
     int32_t gap_blocks;
 };
@@ -94,6 +94,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.resume = off; off = align_up(off + sizeof(int64_t));
     L.Y4 = off; off = align_up(off + 16 * (size_t)n);
     L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
+    L.ga_w = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.total = off;
     return L;
 }
@@ -176,6 +177,15 @@ int variant_ok(srot_handle *h, int variant, const char *who)
         return fail(SROT_EINVAL, "%s: away and pairwise steps use the exact line search (SROT_ELS)", who);
     if (!srot::active_steps_supported(h->S))
         return fail(SROT_EINVAL, "%s: away and pairwise steps support rows of at most 4096 columns", who);
+    return SROT_OK;
+}
+
+int ga_ok(srot_handle *h, const char *who)
+{
+    if (!h) return fail(SROT_EINVAL, "%s: NULL handle", who);
+    if (!srot::ga_supported(h->P, h->S))
+        return fail(SROT_EINVAL, "%s: gap-adaptive sampling supports at most %d rows of at most 4096 columns", who,
+                    (int)srot::GA_MAX_ROWS);
     return SROT_OK;
 }
 
@@ -267,6 +277,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->S.flags = (int32_t *)(base + L.flags);
     h->S.resume = (int64_t *)(base + L.resume);
     h->S.adj_part = (double *)(base + L.adj);
+    h->S.ga_w = (double *)(base + L.ga_w);
 
     int rc = SROT_OK;
     int32_t flag = 0;
@@ -276,6 +287,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     if (e == hipSuccess) e = srot::launch_init_plan(h->P, h->S, h->stream);
     if (e == hipSuccess) e = srot::launch_residual(h->P, h->S, h->stream);
     if (e == hipSuccess) e = srot::launch_mask_build(h->P, h->S, h->stream);
+    if (e == hipSuccess) e = srot::launch_ga_fill(h->P, h->S, nullptr, SROT_GA_INIT, h->stream);
     // the FP32 LMO screen of wide fused rows needs an error bound (see the
     // wide-row chain kernel): 8 u (Cmax + |w| Rmax), doubled, u = 2^-24
     const bool wide = opt->cost == SROT_COST_SQEUCLID && !h->S.own.reg;
@@ -472,6 +484,76 @@ int srot_solve_variant(srot_handle *h, int variant, double *out3, int64_t *passe
             rc = measure_gap(h, out3);
             if (rc != SROT_OK) return rc;
             if (out3[0] <= h->opt.eps) return SROT_OK;
+        }
+    }
+    return SROT_NOT_CONVERGED;
+}
+
+int srot_ga_reset(srot_handle *h, double init)
+{
+    int rc = ga_ok(h, "srot_ga_reset");
+    if (rc != SROT_OK) return rc;
+    if (!(init > 0.0) || !isfinite(init * (double)h->P.m))
+        return fail(SROT_EINVAL, "srot_ga_reset: init must be positive with m * init finite");
+    SROT_HIP(srot::launch_ga_fill(h->P, h->S, nullptr, init, h->stream));
+    return SROT_OK;
+}
+
+int srot_ga_refresh(srot_handle *h)
+{
+    int rc = ga_ok(h, "srot_ga_refresh");
+    if (rc != SROT_OK) return rc;
+    SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
+    SROT_HIP(srot::launch_ga_fill(h->P, h->S, h->S.row_g, 0.0, h->stream));
+    return SROT_OK;
+}
+
+int srot_ga_weights(srot_handle *h, double *W_out)
+{
+    if (!h || !W_out) return fail(SROT_EINVAL, "srot_ga_weights: NULL argument");
+    SROT_HIP(hipMemcpyAsync(W_out, h->S.ga_w, sizeof(double) * (size_t)h->P.m, hipMemcpyDeviceToDevice, h->stream));
+    return SROT_OK;
+}
+
+int srot_step_ga(srot_handle *h, int64_t nsteps, const double *u, int32_t *trace_i, int32_t *trace_j,
+                 double *trace_gamma, double *trace_g)
+{
+    int rc = ga_ok(h, "srot_step_ga");
+    if (rc != SROT_OK) return rc;
+    if (nsteps < 0) return fail(SROT_EINVAL, "srot_step_ga: nsteps < 0");
+    if (nsteps == 0) return SROT_OK;
+    SROT_HIP(srot::launch_ga_steps(h->P, h->S, u, h->opt.seed, h->k, nsteps, h->opt.step_rule, trace_i, trace_j,
+                                   trace_gamma, trace_g, h->stream));
+    h->k += nsteps;
+    return SROT_OK;
+}
+
+int srot_solve_ga(srot_handle *h, double init, int64_t period, double *out3, int64_t *passes)
+{
+    int rc = ga_ok(h, "srot_solve_ga");
+    if (rc != SROT_OK) return rc;
+    if (!out3 || !passes) return fail(SROT_EINVAL, "srot_solve_ga: NULL argument");
+    if (period < 1) return fail(SROT_EINVAL, "srot_solve_ga: period must be >= 1");
+    rc = srot_ga_reset(h, init > 0.0 ? init : SROT_GA_INIT);
+    if (rc != SROT_OK) return rc;
+    *passes = 0;
+    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
+    const int64_t m = h->P.m;
+    for (int64_t p = 0; p < h->opt.max_passes; ++p) {
+        SROT_HIP(srot::launch_ga_steps(h->P, h->S, nullptr, h->opt.seed, h->k, m, h->opt.step_rule, nullptr,
+                                       nullptr, nullptr, nullptr, h->stream));
+        h->k += m;
+        *passes = p + 1;
+        bool swept = false;
+        if ((p + 1) % h->opt.gap_every == 0 || p + 1 == h->opt.max_passes) {
+            rc = measure_gap(h, out3);
+            if (rc != SROT_OK) return rc;
+            if (out3[0] <= h->opt.eps) return SROT_OK;
+            swept = true;
+        }
+        if ((p + 1) % period == 0) {
+            if (!swept) SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
+            SROT_HIP(srot::launch_ga_fill(h->P, h->S, h->S.row_g, 0.0, h->stream));
         }
     }
     return SROT_NOT_CONVERGED;

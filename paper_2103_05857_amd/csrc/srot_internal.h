@@ -49,10 +49,11 @@ struct DeviceState {
     double *partials;      // gap_blocks x 4
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
-    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW tickets, [4] gap-sweep ticket
+    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW ticket
     int64_t *resume;       // step at which the prefetching chain kernel stopped
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
     double screen_delta2;  // 2 x error bound of the FP32 LMO screen (wide fused rows), 0 = unused
+    double *ga_w;          // m, stored block gaps of the gap-adaptive sampler
 };
 
 // Records a printf-style message as the calling thread's last error
@@ -113,6 +114,19 @@ bool active_steps_supported(const DeviceState &S);
 hipError_t launch_active_steps(const ProblemView &P, const DeviceState &S, int pairwise, const int32_t *idx,
                                int64_t nsteps, int32_t *trace_j, int32_t *trace_away, double *trace_gamma,
                                hipStream_t stream);
+
+// Gap-adaptive sampling (srot_ga.hip, Alg. A.4): W lives in LDS during the
+// inner iterations, so at most GA_MAX_ROWS rows; rows of at most 4096 columns.
+constexpr int32_t GA_MAX_ROWS = 16384;
+bool ga_supported(const ProblemView &P, const DeviceState &S);
+// nsteps inner iterations; u (device, nsteps uniforms in [0, 1)) or, when
+// null, u_s from output k0 + s of the block-index stream with key (seed, 0).
+hipError_t launch_ga_steps(const ProblemView &P, const DeviceState &S, const double *u, uint64_t seed, int64_t k0,
+                           int64_t nsteps, int rule, int32_t *trace_i, int32_t *trace_j, double *trace_gamma,
+                           double *trace_g, hipStream_t stream);
+// W_i <- max(src_i, 0) (src: device, m doubles), or W_i <- value when src is null.
+hipError_t launch_ga_fill(const ProblemView &P, const DeviceState &S, const double *src, double value,
+                          hipStream_t stream);
 
 // Barycentric projection (srot_adjoint.hip): Xhat_i = sum_j t_ij y_j / sum_j t_ij.
 hipError_t launch_barycentric(const ProblemView &P, const DeviceState &S, float *Xhat, hipStream_t stream);

@@ -30,6 +30,7 @@ SROT_PERMUTE = 1
 SROT_COST_F32 = 0
 SROT_COST_F64 = 1
 SROT_COST_SQEUCLID = 2
+SROT_GA_INIT = 2.0 ** 300
 
 
 class SrotError(RuntimeError):
@@ -102,6 +103,16 @@ def load():
     L.srot_step_variant.restype = ctypes.c_int
     L.srot_solve_variant.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     L.srot_solve_variant.restype = ctypes.c_int
+    L.srot_ga_reset.argtypes = [_vp, ctypes.c_double]
+    L.srot_ga_reset.restype = ctypes.c_int
+    L.srot_ga_refresh.argtypes = [_vp]
+    L.srot_ga_refresh.restype = ctypes.c_int
+    L.srot_ga_weights.argtypes = [_vp, _vp]
+    L.srot_ga_weights.restype = ctypes.c_int
+    L.srot_step_ga.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
+    L.srot_step_ga.restype = ctypes.c_int
+    L.srot_solve_ga.argtypes = [_vp, ctypes.c_double, _i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    L.srot_solve_ga.restype = ctypes.c_int
     L.srot_barycentric.argtypes = [_vp, _vp]
     L.srot_barycentric.restype = ctypes.c_int
     L.srot_destroy.argtypes = [_vp]
@@ -210,6 +221,31 @@ def srot_solve_variant(h, variant):
     out = (ctypes.c_double * 3)()
     passes = _i64()
     st = _check(load().srot_solve_variant(h, int(variant), out, ctypes.byref(passes)),
+                allow=(SROT_OK, SROT_NOT_CONVERGED))
+    return st, (out[0], out[1], out[2]), passes.value
+
+
+def srot_ga_reset(h, init=SROT_GA_INIT):
+    _check(load().srot_ga_reset(h, float(init)))
+
+
+def srot_ga_refresh(h):
+    _check(load().srot_ga_refresh(h))
+
+
+def srot_ga_weights(h, W_out):
+    _check(load().srot_ga_weights(h, _ptr(W_out)))
+
+
+def srot_step_ga(h, nsteps, u=None, trace_i=None, trace_j=None, trace_gamma=None, trace_g=None):
+    _check(load().srot_step_ga(h, int(nsteps), _ptr(u), _ptr(trace_i), _ptr(trace_j), _ptr(trace_gamma),
+                               _ptr(trace_g)))
+
+
+def srot_solve_ga(h, init=0.0, period=1):
+    out = (ctypes.c_double * 3)()
+    passes = _i64()
+    st = _check(load().srot_solve_ga(h, float(init), int(period), out, ctypes.byref(passes)),
                 allow=(SROT_OK, SROT_NOT_CONVERGED))
     return st, (out[0], out[1], out[2]), passes.value
 

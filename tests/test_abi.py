@@ -86,4 +86,10 @@ def test_null_handle_is_rejected():
     assert L.srot_step(None, 4, None, None, None) == S.SROT_EINVAL
     out = (ctypes.c_double * 3)()
     assert L.srot_gap(None, out, None, None) == S.SROT_EINVAL
+    passes = ctypes.c_int64()
+    assert L.srot_step_ga(None, 4, None, None, None, None, None) == S.SROT_EINVAL
+    assert L.srot_solve_ga(None, 0.0, 1, out, ctypes.byref(passes)) == S.SROT_EINVAL
+    assert L.srot_ga_reset(None, 1.0) == S.SROT_EINVAL
+    assert L.srot_ga_refresh(None) == S.SROT_EINVAL
+    assert L.srot_ga_weights(None, None) == S.SROT_EINVAL
     assert L.srot_strerror(S.SROT_ENONFINITE) == b"non-finite or negative input"
