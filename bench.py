@@ -155,11 +155,11 @@ def main():
     gap_avg_ms = float(np.median(gap_ms))
     gap_bytes = 4.0 * m * n + 12.0 * nnz * m + 8.0 * (3 * m + n)
     gap_achieved = gap_bytes / (gap_avg_ms * 1e-3) / 1e9
-    gap_sweep = dict(kernel="gap_sweep_kernel<f32,4,2>", bound="hbm",
+    gap_sweep = dict(kernel="gap_stream_kernel<f32,2,2>", bound="hbm",
                      achieved=gap_achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                      frac=gap_achieved / HBM_PEAK_GBS, bytes_per_launch=gap_bytes,
                      launch_ms=gap_avg_ms,
-                     traffic=counter_traffic("srot::gap_sweep_kernel<0, 4, 2>"))
+                     traffic=counter_traffic("srot::gap_stream_kernel<0, 2, 2>"))
 
     cpu = None
     if not args.no_cpu:
@@ -241,10 +241,10 @@ def bench_sweep(args):
     # value, 12 B per nonzero), r, b, a and the per-row outputs
     byts = 4.0 * n * n + 12.0 * nnz + 8.0 * (3 * n + 3 * n)
     return {"workload": f"gap sweep, m=n={n} FP32 stored cost (1 GiB), after one pass",
-            "kernel": "gap_sweep_kernel<f32,4,2> (+ 40-byte readback copy)", "bound": "hbm",
+            "kernel": "gap_stream_kernel<f32,2,2> (+ 40-byte readback copy)", "bound": "hbm",
             "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS,
-            "traffic": counter_traffic("srot::gap_sweep_kernel<0, 4, 2>", SWEEP_PROFILE, grid=1024 * 256)}
+            "traffic": counter_traffic("srot::gap_stream_kernel<0, 2, 2>", SWEEP_PROFILE, grid=2048 * 256)}
 
 
 def bench_fw(args, C, a, b):

@@ -88,7 +88,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.j = off; off = align_up(off + sizeof(int32_t) * (size_t)m);
     L.g = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.partials = off;
-    off = align_up(off + sizeof(double) * std::max<size_t>(4 * (size_t)L.gap_blocks, (size_t)srot::fw_finish_blocks(n)));
+    off = align_up(off + sizeof(double) * std::max<size_t>(8 * (size_t)L.gap_blocks, (size_t)srot::fw_finish_blocks(n)));
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.resume = off; off = align_up(off + sizeof(int64_t));

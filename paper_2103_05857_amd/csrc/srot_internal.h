@@ -46,7 +46,7 @@ struct DeviceState {
     double *row_G;         // m, min_j of the block gradient (gap sweep)
     int32_t *row_j;        // m, its lowest argmin
     double *row_g;         // m, per-row gap g_i
-    double *partials;      // gap_blocks x 4
+    double *partials;      // gap_blocks x 8 (gap sweep), or the FW step-size partials
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
     int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW ticket

@@ -517,8 +517,102 @@ __global__ __launch_bounds__(256) void screen_bounds_kernel(ProblemView P, doubl
 // ---------------------------------------------------------------------------
 constexpr int GAP_NT = 256;
 constexpr int GAP_NW = GAP_NT / 64;
-constexpr int GAP_MAX_BLOCKS = 1024;
+constexpr int GAP_MAX_BLOCKS = 2048;
 constexpr int GAP_KS = 2;  // support entries per lane and row gathered ahead of the scan
+
+// Workgroup partials of a gap sweep and the final sums.  Each workgroup adds
+// its rows' (a_i G_i, lin_i, g_i) and, for its slice of ceil(n / grid)
+// columns, ||r||^2 and <b, r>; the five partials travel through device-scope
+// atomics (performed at the coherent level, so no cache write-back is
+// needed), and the last workgroup to finish adds them in a fixed order: each
+// thread its strided workgroups (all requested at once), then the wave
+// (DPP), then the four waves in order.  At most GAP_MAX_BLOCKS workgroups.
+__device__ __forceinline__ void gap_finish(const ProblemView &P, const double *__restrict__ rg, double aG,
+                                           double lin, double gs, double *__restrict__ partials,
+                                           int32_t *__restrict__ ticket, double *__restrict__ out)
+{
+    constexpr int PER = GAP_MAX_BLOCKS / GAP_NT;  // workgroups per thread in the final sum
+    __shared__ double s_w[GAP_NW][5];
+    __shared__ double s_red[GAP_NW * 5];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = P.n;
+    const double w = P.w;
+    const int nb = (int)gridDim.x;
+    const int cols = (n + nb - 1) / nb;
+    const int j0 = min(n, (int)blockIdx.x * cols), j1 = min(n, j0 + cols);
+    double x[2] = {0.0, 0.0};  // ||r||^2, <b, r> over this workgroup's columns
+    for (int j = j0 + tid; j < j1; j += GAP_NT) {
+        const double rj = rg[j];
+        x[0] += rj * rj;
+        x[1] += P.b[j] * rj;
+    }
+    wave_sum<2>(x);
+    if (lane == 0) { s_w[wid][0] = aG; s_w[wid][1] = lin; s_w[wid][2] = gs; s_w[wid][3] = x[0]; s_w[wid][4] = x[1]; }
+    __syncthreads();
+    // The ticket increment takes an operand computed from the values the
+    // exchanges return, so it is issued only after every partial has landed.
+    if (tid == 0) {
+        double t5[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            t5[c] = s_w[0][c];
+#pragma unroll
+            for (int k = 1; k < GAP_NW; ++k) t5[c] += s_w[k][c];
+        }
+        unsigned long long seen = 0ull;
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            seen ^= __hip_atomic_exchange(reinterpret_cast<unsigned long long *>(partials) + 8 * blockIdx.x + c,
+                                          (unsigned long long)__double_as_longlong(t5[c]), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        int zero;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(zero) : "v"((unsigned)(seen ^ (seen >> 32))));
+        const int got = __hip_atomic_fetch_add(ticket, 1 + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (got == nb - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    double v[PER][5];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int k = tid + q * GAP_NT;
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            v[q][c] = (k < nb) ? __longlong_as_double((long long)__hip_atomic_load(
+                                     reinterpret_cast<unsigned long long *>(partials) + 8 * k + c, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT))
+                               : 0.0;
+    }
+    double f5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // a_i G_i, lin, g, ||r||^2, <b, r>
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) f5[c] += v[q][c];
+    }
+    wave_sum<5>(f5);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s_red[wid * 5 + c] = f5[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t5[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            t5[c] = s_red[c];
+#pragma unroll
+            for (int q = 1; q < GAP_NW; ++q) t5[c] += s_red[q * 5 + c];
+        }
+        const double pa = t5[0], pl = t5[1], pg = t5[2], rr = t5[3], br = t5[4];
+        out[0] = pg;
+        out[1] = pl + 0.5 * w * rr;
+        out[2] = pa - w * br - 0.5 * w * rr;
+        out[3] = pl;
+        out[4] = rr;
+        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 template <int COST, int VEC, int R>
 __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const double *__restrict__ T,
@@ -534,10 +628,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const 
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int GU = 16 / VEC;  // vectors per lane per group: 16 columns
-    __shared__ double s_w[GAP_NW][3];
-    __shared__ double s_red[GAP_NW * 5];
-    __shared__ int s_last;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int m = P.m, n = P.n;
     const double w = P.w;
     const CT *__restrict__ C = (const CT *)P.C;
@@ -706,69 +797,205 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const 
             gs += x[0];
         }
     }
-    if (lane == 0) { s_w[wid][0] = aG; s_w[wid][1] = lin; s_w[wid][2] = gs; }
-    __syncthreads();
-    // Partials travel through device-scope atomics, which are performed at the
-    // coherent level; no cache write-back is needed.  The ticket increment
-    // takes an operand computed from the values the exchanges return, so it
-    // is issued only after every partial has landed.
-    if (tid == 0) {
-        double t3[3] = {s_w[0][0], s_w[0][1], s_w[0][2]};
+    gap_finish(P, rg, aG, lin, gs, partials, ticket, out);
+}
+
+// Stored-cost gap sweep with the memory operations ordered for latency:
+// per group of R rows a wave issues the rows' support-mask words (up to
+// GAP_MW per lane and row), then the first batch of GU 16-byte cost vectors
+// per row together with the matching entries of r, and only then waits for
+// the masks; the support gathers follow, and the batches run double
+// buffered (batch q + 1 requested before batch q is consumed).  Loads are
+// raw buffer loads whose out-of-range offsets return zero without touching
+// memory, so every batch is one fixed, branch-free group of requests and
+// each wait covers exactly the batch it needs.  Same per-row results and
+// summation order as gap_sweep_kernel.
+constexpr int GAP_MW = 8;  // mask words per lane and row read ahead
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int COST, int R, int GU>
+__global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, const double *__restrict__ T,
+                                                            const double *__restrict__ rg,
+                                                            const uint32_t *__restrict__ M, Ownership own,
+                                                            double *__restrict__ row_G,
+                                                            int32_t *__restrict__ row_j,
+                                                            double *__restrict__ row_g,
+                                                            double *__restrict__ partials,
+                                                            int32_t *__restrict__ ticket,
+                                                            double *__restrict__ out)
+{
+    using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
+    constexpr int VEC = 16 / (int)sizeof(CT);  // columns per 16-byte vector
+    constexpr int RV = VEC / 2;                // 16-byte vectors of r per cost vector
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int m = P.m, n = P.n;
+    const double w = P.w;
+    const CT *__restrict__ C = (const CT *)P.C;
+    const int slots = own.words * own.nt;
+    const int nq = (n + 64 * VEC - 1) / (64 * VEC);
+    const __amdgpu_buffer_rsrc_t rs_r = buf_rsrc(rg, (unsigned)n * 8u);
+
+    double aG = 0.0, lin = 0.0, gs = 0.0;
+    const int stride = gridDim.x * GAP_NW * R;
+    for (int i0 = (blockIdx.x * GAP_NW + wid) * R; i0 < m; i0 += stride) {
+        int ir[R];
+        __amdgpu_buffer_rsrc_t rs_c[R];
+        uint32_t mw[R][GAP_MW];
 #pragma unroll
-        for (int k = 1; k < GAP_NW; ++k) { t3[0] += s_w[k][0]; t3[1] += s_w[k][1]; t3[2] += s_w[k][2]; }
-        unsigned long long seen = 0ull;
+        for (int k = 0; k < R; ++k) {
+            ir[k] = (i0 + k < m) ? i0 + k : m - 1;
+            rs_c[k] = buf_rsrc(C + (size_t)ir[k] * (size_t)n, (unsigned)(n * sizeof(CT)));
+            // rows past the end read an empty range: no support, no cost
+            const __amdgpu_buffer_rsrc_t rs_m =
+                buf_rsrc(M + (size_t)ir[k] * slots, (i0 + k < m) ? (unsigned)slots * 4u : 0u);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            seen ^= __hip_atomic_exchange(reinterpret_cast<unsigned long long *>(partials) + 4 * blockIdx.x + k,
-                                          (unsigned long long)__double_as_longlong(t3[k]), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        int zero;
-        asm volatile("v_mov_b32 %0, 0" : "=v"(zero) : "v"((unsigned)(seen ^ (seen >> 32))));
-        const int got = __hip_atomic_fetch_add(ticket, 1 + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (got == (int)gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    auto part = [&](int k, int c) -> double {
-        return __longlong_as_double((long long)__hip_atomic_load(
-            reinterpret_cast<unsigned long long *>(partials) + 4 * k + c, __ATOMIC_RELAXED,
-            __HIP_MEMORY_SCOPE_AGENT));
-    };
-    // fixed order: each thread's strided terms in index order, then the wave
-    // (DPP), then the four waves in order
-    double f5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // a_i G_i, lin, g, ||r||^2, <b, r>
-    for (int k = tid; k < (int)gridDim.x; k += GAP_NT) {
-        f5[0] += part(k, 0);
-        f5[1] += part(k, 1);
-        f5[2] += part(k, 2);
-    }
-    for (int j = tid; j < n; j += GAP_NT) {
-        const double rj = rg[j];
-        f5[3] += rj * rj;
-        f5[4] += P.b[j] * rj;
-    }
-    wave_sum<5>(f5);
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) s_red[wid * 5 + c] = f5[c];
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t5[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            t5[c] = s_red[c];
-#pragma unroll
-            for (int q = 1; q < GAP_NW; ++q) t5[c] += s_red[q * 5 + c];
+            for (int q = 0; q < GAP_MW; ++q)
+                mw[k][q] = __builtin_amdgcn_raw_buffer_load_b32(rs_m, (int)((lane + 64 * q) * 4), 0, 0);
         }
-        const double pa = t5[0], pl = t5[1], pg = t5[2], rr = t5[3], br = t5[4];
-        out[0] = pg;
-        out[1] = pl + 0.5 * w * rr;
-        out[2] = pa - w * br - 0.5 * w * rr;
-        out[3] = pl;
-        out[4] = rr;
-        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u32x4 ca[R][GU], cb[R][GU];
+        u32x4 ra[GU][RV], rb[GU][RV];
+        auto issue = [&](u32x4 (&c)[R][GU], u32x4 (&rr)[GU][RV], int q0) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int jb = ((q0 + u) * 64 + lane) * VEC;
+                const unsigned oc = jb < n ? (unsigned)jb * (unsigned)sizeof(CT) : kOOB;
+                const unsigned orr = jb < n ? (unsigned)jb * 8u : kOOB;
+#pragma unroll
+                for (int k = 0; k < R; ++k) c[k][u] = __builtin_amdgcn_raw_buffer_load_b128(rs_c[k], (int)oc, 0, 0);
+#pragma unroll
+                for (int h = 0; h < RV; ++h)
+                    rr[u][h] = __builtin_amdgcn_raw_buffer_load_b128(rs_r, (int)(orr + 16u * h), 0, 0);
+            }
+        };
+        double best[R];
+        int bj[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) { best[k] = INFINITY; bj[k] = 0x7fffffff; }
+        auto consume = [&](const u32x4 (&c)[R][GU], const u32x4 (&rr)[GU][RV], int q0) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int jb = ((q0 + u) * 64 + lane) * VEC;
+                double rv[VEC];
+#pragma unroll
+                for (int h = 0; h < RV; ++h) {
+                    rv[2 * h] = __builtin_bit_cast(double, (unsigned long long)rr[u][h].x | ((unsigned long long)rr[u][h].y << 32));
+                    rv[2 * h + 1] = __builtin_bit_cast(double, (unsigned long long)rr[u][h].z | ((unsigned long long)rr[u][h].w << 32));
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        double cval;
+                        if constexpr (sizeof(CT) == 4) {
+                            const unsigned bits = e == 0 ? c[k][u].x : (e == 1 ? c[k][u].y : (e == 2 ? c[k][u].z : c[k][u].w));
+                            cval = (double)__builtin_bit_cast(float, bits);
+                        } else {
+                            const unsigned lo = e == 0 ? c[k][u].x : c[k][u].z, hi = e == 0 ? c[k][u].y : c[k][u].w;
+                            cval = __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+                        }
+                        const double v = (jb < n) ? cval + w * rv[e] : INFINITY;
+                        if (v < best[k]) { best[k] = v; bj[k] = jb + e; }
+                    }
+                }
+            }
+        };
+        issue(ca, ra, 0);
+
+        // support entries of the rows from the mask words (first GAP_KS per
+        // lane and row gathered now, further ones after the scan)
+        int sj[R][GAP_KS];
+        double st[R][GAP_KS], sc[R][GAP_KS], sr[R][GAP_KS];
+        bool more[R];
+        int nfound[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            more[k] = false;
+            int found = 0;
+#pragma unroll
+            for (int e = 0; e < GAP_KS; ++e) sj[k][e] = -1;
+            for (int q = 0; q < GAP_MW; ++q) {
+                uint32_t mk = mw[k][q];
+                const int sl = lane + 64 * q;
+                const int wd = sl / own.nt, ts = sl - wd * own.nt;
+                while (mk) {
+                    const int b = __ffs(mk) - 1;
+                    mk &= mk - 1u;
+                    const int u = wd * 32 + b;
+                    const int j = ((u / own.vec) * own.nt + ts) * own.vec + (u % own.vec);
+                    if (found < GAP_KS) {
+#pragma unroll
+                        for (int e = 0; e < GAP_KS; ++e) sj[k][e] = (e == found) ? j : sj[k][e];
+                        ++found;
+                    } else {
+                        more[k] = true;
+                    }
+                }
+            }
+            nfound[k] = found;
+            more[k] |= (slots > 64 * GAP_MW) && (i0 + k < m);
+#pragma unroll
+            for (int e = 0; e < GAP_KS; ++e) {
+                const int j = sj[k][e] >= 0 ? sj[k][e] : 0;
+                st[k][e] = T[(size_t)ir[k] * (size_t)n + j];
+                sr[k][e] = rg[j];
+                sc[k][e] = (double)C[(size_t)ir[k] * (size_t)n + j];
+            }
+        }
+
+        for (int q0 = 0; q0 < nq; q0 += 2 * GU) {
+            issue(cb, rb, q0 + GU);
+            consume(ca, ra, q0);
+            issue(ca, ra, q0 + 2 * GU);
+            consume(cb, rb, q0 + GU);
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (i0 + k >= m) break;  // uniform over the wave
+            const int i = i0 + k;
+            double G = best[k];
+            int J = bj[k];
+            wave_argmin(G, J);
+            double x[2] = {0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < GAP_KS; ++e) {
+                if (sj[k][e] >= 0) {
+                    x[0] += st[k][e] * (sc[k][e] + w * sr[k][e] - G);
+                    x[1] += st[k][e] * sc[k][e];
+                }
+            }
+            if (__any(more[k])) {
+                // every support entry of this lane after the ones gathered
+                // above (its first nfound, in slot order)
+                int seen = 0;
+                for (int sl = lane; sl < slots; sl += 64) {
+                    const int wd = sl / own.nt, ts = sl - wd * own.nt;
+                    uint32_t mk = M[(size_t)i * slots + sl];
+                    while (mk) {
+                        const int b = __ffs(mk) - 1;
+                        mk &= mk - 1u;
+                        if (seen++ < nfound[k]) continue;
+                        const int u = wd * 32 + b;
+                        const int j = ((u / own.vec) * own.nt + ts) * own.vec + (u % own.vec);
+                        const double t = T[(size_t)i * (size_t)n + j];
+                        const double c = (double)C[(size_t)i * (size_t)n + j];
+                        x[0] += t * (c + w * rg[j] - G);
+                        x[1] += t * c;
+                    }
+                }
+            }
+            wave_sum<2>(x);
+            if (lane == 0) {
+                row_G[i] = G;
+                row_j[i] = J;
+                row_g[i] = x[0];
+            }
+            aG += P.a[i] * G;
+            lin += x[1];
+            gs += x[0];
+        }
     }
+    gap_finish(P, rg, aG, lin, gs, partials, ticket, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1108,45 +1335,56 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
     }
 }
 
+// Workgroups of a gap sweep: two rows per wave, four waves per workgroup.
 int32_t gap_blocks_for(int64_t m)
 {
-    int64_t b = (m + GAP_NW - 1) / GAP_NW;
+    int64_t b = (m + 2 * GAP_NW - 1) / (2 * GAP_NW);
     if (b < 1) b = 1;
     if (b > GAP_MAX_BLOCKS) b = GAP_MAX_BLOCKS;
     return (int32_t)b;
 }
 
-template <int COST, int VEC, int R>
+// Row-strided sweep (fused cost, or rows not split into 16-byte vectors):
+// at most 1024 workgroups, where it measured best.
+template <int COST, int VEC>
 static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, hipStream_t st)
 {
+    constexpr int R = 2;  // each r_j read serves both rows
     const int64_t waves = (P.m + R - 1) / R;
-    const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, GAP_MAX_BLOCKS),
-                                          S.gap_blocks);
+    const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, 1024), S.gap_blocks);
     hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
                        S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars);
     return hipGetLastError();
 }
 
-// Two rows per wave: each r_j read serves both; more rows per wave would
-// cost occupancy (registers) for little further saving.
-template <int COST, int VEC>
-static hipError_t launch_gap_vec(const ProblemView &P, const DeviceState &S, hipStream_t st)
+// Stored cost in 16-byte vectors: two rows per wave, double-buffered
+// batches of two vectors (FP32) or four (FP64) per lane and row.
+template <int COST>
+static hipError_t launch_gap_stream(const ProblemView &P, const DeviceState &S, hipStream_t st)
 {
-    return launch_gap_rows<COST, VEC, 2>(P, S, st);
+    constexpr int R = 2, GU = (COST == SROT_COST_F32) ? 2 : 4;
+    const int64_t waves = (P.m + R - 1) / R;
+    const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, GAP_MAX_BLOCKS),
+                                          S.gap_blocks);
+    hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
+                       S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars);
+    return hipGetLastError();
 }
 
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream)
 {
     const uintptr_t cbase = (uintptr_t)P.C;
+    // buffer ranges of one cost row and of r are 32-bit byte counts
+    const bool ranged = (int64_t)P.n * 8 < (int64_t)0x7fffffff;
     switch (P.cost) {
     case SROT_COST_F32:
-        if (P.n % 4 == 0 && cbase % 16 == 0) return launch_gap_vec<SROT_COST_F32, 4>(P, S, stream);
-        return launch_gap_vec<SROT_COST_F32, 1>(P, S, stream);
+        if (P.n % 4 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F32>(P, S, stream);
+        return launch_gap_rows<SROT_COST_F32, 1>(P, S, stream);
     case SROT_COST_F64:
-        if (P.n % 2 == 0 && cbase % 16 == 0) return launch_gap_vec<SROT_COST_F64, 2>(P, S, stream);
-        return launch_gap_vec<SROT_COST_F64, 1>(P, S, stream);
+        if (P.n % 2 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F64>(P, S, stream);
+        return launch_gap_rows<SROT_COST_F64, 1>(P, S, stream);
     default:
-        return launch_gap_vec<SROT_COST_SQEUCLID, 1>(P, S, stream);
+        return launch_gap_rows<SROT_COST_SQEUCLID, 1>(P, S, stream);
     }
 }
 
