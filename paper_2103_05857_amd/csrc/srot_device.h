@@ -304,7 +304,7 @@ struct RowSlot {
     float x[3];
 };
 
-constexpr int KA = 4;  // atoms per (row, thread) handled by the prefetching kernel
+constexpr int KA = 2;  // atoms per (row, thread) handled by the prefetching kernel
 
 template <typename CT>
 struct AtomSlot {
@@ -365,18 +365,6 @@ __device__ __forceinline__ double wave_min(double v)
     m = fmin(m, readlane_f64(v, 32));
     m = fmin(m, readlane_f64(v, 48));
     return m;
-}
-
-// Sum of x over the lanes set in `lanes`, in lane order (wave-uniform result).
-__device__ __forceinline__ double lanes_sum(double x, unsigned long long lanes)
-{
-    double s = 0.0;
-    while (lanes) {
-        const int l = __ffsll((long long)lanes) - 1;
-        lanes &= lanes - 1ull;
-        s += readlane_f64(x, l);
-    }
-    return s;
 }
 
 template <int NT, int CPT, int VEC, int COST, bool TRACE>
@@ -512,11 +500,27 @@ __device__ __forceinline__ int64_t chain_fast(const ProblemView &P, double *__re
                 for (int u = 0; u < CPT; ++u)
                     vv[u] = (owned_col<NT, VEC>(u, tid) < n) ? vv[u] : INFINITY;
             }
+            {
+                // pairwise tree: the minimum is exact in any order
+                double t[CPT];
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) best = fmin(best, vv[u]);
-            int bj = 0x7fffffff;
+                for (int u = 0; u < CPT; ++u) t[u] = vv[u];
 #pragma unroll
-            for (int u = CPT - 1; u >= 0; --u) bj = (vv[u] == best) ? owned_col<NT, VEC>(u, tid) : bj;
+                for (int h = CPT / 2; h >= 1; h /= 2) {
+#pragma unroll
+                    for (int u = 0; u < h; ++u) t[u] = fmin(t[u], t[u + h]);
+                }
+                best = t[0];
+            }
+            // lowest owned column holding the minimum (owned_col grows with u)
+            int bj;
+            {
+                unsigned bits = 0u;
+#pragma unroll
+                for (int u = 0; u < CPT; ++u) bits |= (vv[u] == best) ? (1u << u) : 0u;
+                const int us0 = __ffs(bits) - 1;
+                bj = ((us0 / VEC) * NT + tid) * VEC + (us0 % VEC);
+            }
 
             // the wave's LMO candidate (eq. SemiRelaxedSubproblemImplement)
             WavePart wp;
@@ -549,11 +553,21 @@ __device__ __forceinline__ int64_t chain_fast(const ProblemView &P, double *__re
                     tj += at_j ? t : 0.0;
                     ts += t;
                 }
-                const unsigned long long act = __ballot((mk != 0u) && (p != 0.0 || q2 != 0.0 || tj != 0.0 || ts != 0.0));
-                wp.P = lanes_sum(p, act);
-                wp.Q = lanes_sum(q2, act);
-                wp.tj = lanes_sum(tj, act);
-                wp.Ts = lanes_sum(ts, act);
+                unsigned long long act = __ballot((mk != 0u) && (p != 0.0 || q2 != 0.0 || tj != 0.0 || ts != 0.0));
+                // each sum over the active lanes in lane order
+                double sp = 0.0, sq = 0.0, sj = 0.0, ss = 0.0;
+                while (act) {
+                    const int l = __ffsll((long long)act) - 1;
+                    act &= act - 1ull;
+                    sp += readlane_f64(p, l);
+                    sq += readlane_f64(q2, l);
+                    sj += readlane_f64(tj, l);
+                    ss += readlane_f64(ts, l);
+                }
+                wp.P = sp;
+                wp.Q = sq;
+                wp.tj = sj;
+                wp.Ts = ss;
                 wp.more = __any(more) ? 1 : 0;
             }
             // one exchange per step: merge the waves' partials in wave order
@@ -561,9 +575,16 @@ __device__ __forceinline__ int64_t chain_fast(const ProblemView &P, double *__re
             if (NW > 1) {
                 if (lane == 0) s_part[s & 1][wid] = wp;
                 __syncthreads();
-                gp = s_part[s & 1][0];
+                // pairwise tree over the waves (fixed order)
+                WavePart t[NW];
 #pragma unroll
-                for (int k = 1; k < NW; ++k) gp = wave_part_merge(gp, s_part[s & 1][k]);
+                for (int k = 0; k < NW; ++k) t[k] = s_part[s & 1][k];
+#pragma unroll
+                for (int h = 1; h < NW; h *= 2) {
+#pragma unroll
+                    for (int k = 0; k + h < NW; k += 2 * h) t[k] = wave_part_merge(t[k], t[k + h]);
+                }
+                gp = t[0];
             }
             if (gp.more) { stop = true; done = s; break; }
             const int jstar = gp.j;
