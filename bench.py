@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS_SRC = os.path.join(ROOT, "paper_2103_05857_amd", "csrc", "srot_kernels.hip")
+KERNELS_SRC = [os.path.join(ROOT, "paper_2103_05857_amd", "csrc", f) for f in ("srot_kernels.hip", "srot_device.h")]
 PROFILE = os.path.join(ROOT, "profiles", "chain_gap_stored_f32_m4096_n4096.md")
 SWEEP_PROFILE = os.path.join(ROOT, "profiles", "gap_sweep_stored_f32_m16384_n16384.md")
 
@@ -37,7 +37,7 @@ def counter_traffic(kernel_prefix, profile=PROFILE, grid=None):
     try:
         text = open(profile).read()
         blob = json.loads(re.findall(r"```json\n(.*?)\n```", text, flags=re.S)[-1])
-        sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()[:16]
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNELS_SRC)).hexdigest()[:16]
     except (OSError, IndexError, ValueError):
         return None
     if blob.get("kernels_sha256") != sha:
