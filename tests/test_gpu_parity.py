@@ -151,12 +151,19 @@ def test_solve_stops_at_same_pass_as_oracle():
     assert g <= 1e-6
 
 
-@pytest.mark.parametrize("cost_mode", ["stored", "sqeuclid"])
-def test_gap_sweep_on_given_plans(cost_mode):
+@pytest.mark.parametrize("cost_mode,dtype", [("stored", np.float32), ("stored", np.float64),
+                                             ("sqeuclid", np.float32)])
+def test_gap_sweep_on_given_plans(cost_mode, dtype):
+    """Shapes cover the row-strided sweep (odd widths, the fused cost) and
+    the vector-stream sweep (widths divisible by the vector), with support
+    masks of up to 512 words per row read ahead and wider ones (n = 20000)
+    taking the slow path; about 5% of each row is in the support."""
     _need_gpu()
     rng = np.random.default_rng(3)
-    for (m, n, w) in [(1, 1, 1.0), (1, 9, 2.0), (17, 1, 0.5), (130, 257, 1.0), (64, 5003, 10.0)]:
-        d = I.problem_mixture(7, m, n, cost_dtype=np.float32)
+    shapes = [(1, 1, 1.0), (1, 9, 2.0), (17, 1, 0.5), (130, 257, 1.0), (64, 5003, 10.0),
+              (130, 256, 1.0), (64, 5004, 10.0), (6, 20000, 1.0)]
+    for (m, n, w) in shapes:
+        d = I.problem_mixture(7, m, n, cost_dtype=dtype)
         T = rng.random((m, n)) * (rng.random((m, n)) < 0.05)
         T[np.arange(m), rng.integers(0, n, m)] += 0.3
         T = T / T.sum(axis=1, keepdims=True) * d["a"][:, None]
