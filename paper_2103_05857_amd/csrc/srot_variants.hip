@@ -56,25 +56,50 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
         const int j = owned_col<NT, VEC>(u, tid);
         r[u] = (j < n) ? rg[j] : 0.0;
     }
+    // One step ahead: the next row's cost entries, mask word and a_i are
+    // requested at the start of a step, its plan entries once the mask has
+    // arrived (after the step's first reductions); when the next step
+    // revisits the row, the entries come from the update instead.
+    auto load_row = [&](int i, CT (&cv)[CPT], float (&x)[3], uint32_t &mk, double &ai) {
+        ai = P.a[i];
+        mk = M[(size_t)i * NT + tid];
+        if constexpr (FUSED) { x[0] = P.X[3 * i]; x[1] = P.X[3 * i + 1]; x[2] = P.X[3 * i + 2]; }
+        else load_cost_row<NT, CPT, VEC, CT>(C + (size_t)i * (size_t)n, n, tid, cv);
+    };
+    auto gather = [&](int i, uint32_t mk, double (&t)[CPT]) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            t[u] = (mk & (1u << u)) ? T[(size_t)i * (size_t)n + j] : 0.0;
+        }
+    };
+    int i = idx[0];
+    CT cv[CPT];
+    float x[3] = {0.f, 0.f, 0.f};
+    uint32_t mk;
+    double ai, t[CPT];
+    load_row(i, cv, x, mk, ai);
+    gather(i, mk, t);
+    int inext = nsteps > 1 ? idx[1] : i;
+
     for (int64_t s = 0; s < nsteps; ++s) {
-        const int i = idx[s];
-        const double ai = P.a[i];
+        CT cvn[CPT];
+        float xn[3] = {0.f, 0.f, 0.f};
+        uint32_t mkn;
+        double an, tnx[CPT];
+        load_row(inext, cvn, xn, mkn, an);
+        const int inext2 = (s + 2 < nsteps) ? idx[s + 2] : inext;
         const size_t base = (size_t)i * (size_t)n;
-        const uint32_t mk = M[(size_t)i * NT + tid];
-        CT cv[CPT];
-        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-        if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
-        else load_cost_row<NT, CPT, VEC, CT>(C + base, n, tid, cv);
-        double t[CPT], vv[CPT];
+
+        double vv[CPT];
         double best = INFINITY, nb = INFINITY;
         int bj = 0x7fffffff, nj = 0x7fffffff;
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int j = owned_col<NT, VEC>(u, tid);
             const int jc = j < n ? j : n - 1;
-            t[u] = (mk & (1u << u)) ? T[base + j] : 0.0;
             double c;
-            if constexpr (FUSED) c = sqdist(x0, x1, x2, P.Y[3 * jc], P.Y[3 * jc + 1], P.Y[3 * jc + 2]);
+            if constexpr (FUSED) c = sqdist(x[0], x[1], x[2], P.Y[3 * jc], P.Y[3 * jc + 1], P.Y[3 * jc + 2]);
             else c = (double)cv[u];
             vv[u] = c + w * r[u];
             const double v = (j < n) ? vv[u] : INFINITY;
@@ -85,6 +110,7 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
         block_argmin<NW>(nb, nj, s_v2[s & 1], s_j2[s & 1]);
         const double G = best, V = -nb;
         const int js = bj, ja = nj;
+        if (inext != i) gather(inext, mkn, tnx);
 
         // P1 = sum t (g - G), P2 = sum t (V - g), Q1 = sum_{j != js} t^2,
         // Q2 = sum_{j != ja} t^2, t_js, t_ja, number of atoms
@@ -141,6 +167,7 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
             if (j < n && tn != t[u]) T[base + j] = tn;
             r[u] += tn - t[u];
             nm = (tn != 0.0) ? (nm | (1u << u)) : (nm & ~(1u << u));
+            t[u] = tn;
         }
         if (nm != mk) M[(size_t)i * NT + tid] = nm;
         if (tid == 0) {
@@ -148,6 +175,20 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
             if (trace_away) trace_away[s] = fw_dir ? -1 - ja : ja;
             if (trace_gamma) trace_gamma[s] = gamma;
         }
+
+        // the next step's row
+        if (inext == i) {
+            mkn = nm;
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) tnx[u] = t[u];
+        }
+        i = inext;
+        inext = inext2;
+        mk = mkn;
+        ai = an;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) { cv[u] = cvn[u]; t[u] = tnx[u]; }
+        x[0] = xn[0]; x[1] = xn[1]; x[2] = xn[2];
     }
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
