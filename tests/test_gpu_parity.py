@@ -283,6 +283,39 @@ def test_wide_rows_with_repeated_points_in_one_thread(n):
     np.testing.assert_allclose(gg.cpu().numpy()[:first], otr[1][:first], rtol=0, atol=1e-9)
 
 
+def test_rows_with_more_atoms_per_thread_than_prefetched():
+    """Rows whose support holds three or four columns of one thread (adjacent
+    columns of one 16-byte group) exceed the support entries the prefetching
+    chain reads ahead; the chain then stops and the tail kernel finishes the
+    launch.  The first such row is visited after 50 ordinary steps."""
+    _need_gpu()
+    m, n, w = 64, 1024, 1.0
+    d = I.problem_mixture(19, m, n)
+    a = d["a"]
+    T = np.zeros((m, n))
+    T[:, 0] = a
+    for i in range(8):                      # four adjacent columns: one thread
+        T[i, 0] = 0.0
+        T[i, 4:8] = a[i] / 4
+    for i in range(8, 16):                  # three adjacent columns
+        T[i, 0] = 0.0
+        T[i, 8:11] = a[i] / 3
+    rng = np.random.default_rng(2)
+    idx = np.concatenate([rng.integers(16, m, 50), np.tile(np.arange(16), 3),
+                          rng.integers(0, m, 200)]).astype(np.int32)
+    P = _oracle_problem(d, "stored", w)
+    st = O.State(P, T)
+    otr = O.bcfw_steps(P, st, idx, rule=O.ELS)
+    sol = _gpu_problem(d, "stored", w)
+    sol.set_state(torch.from_numpy(T).to(DEV), 0)
+    gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
+    _compare_traces(otr, gj, gg)
+    Tg, r = sol.plan()
+    Tg = Tg.cpu().numpy()
+    np.testing.assert_allclose(Tg, st.T, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r.cpu().numpy(), Tg.sum(axis=0) - d["b"], rtol=0, atol=1e-13)
+
+
 def test_resume_from_checkpoint_repeats_the_run():
     _need_gpu()
     m, n = 128, 300
