@@ -53,7 +53,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, resume, Y4, adj, ga_w, total;
+    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, slow, Y4, adj, ga_w, total;
     int64_t idx_cap;
     int32_t gap_blocks;
 };
@@ -91,7 +91,7 @@ Layout make_layout(int64_t m, int64_t n)
     off = align_up(off + sizeof(double) * std::max<size_t>(8 * (size_t)L.gap_blocks, (size_t)srot::fw_finish_blocks(n)));
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
-    L.resume = off; off = align_up(off + sizeof(int64_t));
+    L.slow = off; off = align_up(off + sizeof(int64_t));
     L.Y4 = off; off = align_up(off + 16 * (size_t)n);
     L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
     L.ga_w = off; off = align_up(off + sizeof(double) * (size_t)m);
@@ -275,7 +275,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->S.gap_blocks = L.gap_blocks;
     h->S.scalars = (double *)(base + L.scalars);
     h->S.flags = (int32_t *)(base + L.flags);
-    h->S.resume = (int64_t *)(base + L.resume);
+    h->S.slow_steps = (int64_t *)(base + L.slow);
     h->S.adj_part = (double *)(base + L.adj);
     h->S.ga_w = (double *)(base + L.ga_w);
 

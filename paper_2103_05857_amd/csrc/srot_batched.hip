@@ -5,9 +5,9 @@
 // with the block indices drawn on the device from the counter-based Philox
 // stream, the duality-gap sweep (Thm 2) every gap_every passes and the stop
 // test g <= eps -- no host round trip until every problem is done.  The
-// per-problem work reuses the single-problem chain (chain_fast, then
-// chain_tail from where it stopped), so a problem solved here follows the
-// same trajectory as srot_solve with the same tile shape and seed.
+// per-problem work reuses the single-problem chain (chain_run), so a
+// problem solved here follows the same trajectory as srot_solve with the
+// same tile shape and seed.
 //
 // Problems are grouped by tile shape (threads x columns per thread x vector
 // width); each group is one launch of batch_solve_kernel, one workgroup per
@@ -195,9 +195,7 @@ __global__ __launch_bounds__(NT) void batch_solve_kernel(const float *__restrict
         for (int s = tid; s < m; s += NT)
             idx[s] = (int32_t)__umul64hi(philox_output(prm.seed, (uint64_t)(k + s)), (uint64_t)m);
         __syncthreads();
-        const int64_t done = chain_fast<NT, CPT, VEC, COST, false>(P, T, rg, M, idx, k, m, prm.rule,
-                                                                   nullptr, nullptr);
-        chain_tail<NT, CPT, VEC, COST>(P, T, rg, M, idx, k, done, m, prm.rule, nullptr, nullptr);
+        chain_run<NT, CPT, VEC, COST, false>(P, T, rg, M, idx, k, m, prm.rule, nullptr, nullptr);
         k += m;
         passes = pass + 1;
         if (passes % prm.gap_every == 0 || passes == prm.max_passes) {

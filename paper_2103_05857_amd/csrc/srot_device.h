@@ -289,11 +289,11 @@ __device__ __forceinline__ double blend(double t, double gamma, double add)
 // vector-memory operations exact, so the prefetched rows (DA ahead) and
 // atoms (2 ahead) are waited on individually.  A row updated after its data
 // was requested is patched from registers.  If a thread's row holds more
-// than KA atoms (rare), or once the last full group of DA steps is done, the
-// kernel stops and records the step to resume from.
+// than KA atoms (rare), or once the last full group of DA steps is done,
+// chain_fast returns the step it reached.
 //
-// chain_tail_kernel finishes the remaining steps one at a time with plain
-// loads of every support entry (no prefetch, any support size).
+// chain_tail takes steps one at a time with plain loads of every support
+// entry (no prefetch, any support size); chain_run alternates the two.
 // ---------------------------------------------------------------------------
 template <int CPT, typename CT>
 struct RowSlot {
@@ -304,7 +304,8 @@ struct RowSlot {
     float x[3];
 };
 
-constexpr int KA = 2;  // atoms per (row, thread) handled by the prefetching kernel
+constexpr int KA = 2;        // atoms per (row, thread) handled by the prefetching chain
+constexpr int CHAIN_DA = 4;  // rows requested ahead (cost row, mask, a_i)
 
 template <typename CT>
 struct AtomSlot {
@@ -379,7 +380,7 @@ __device__ __forceinline__ int64_t chain_fast(const ProblemView &P, double *__re
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NW = NT / 64;
-    constexpr int DA = 4;  // rows requested ahead (cost row, mask, a_i)
+    constexpr int DA = CHAIN_DA;
     __shared__ double r_lds[CPT * NT];      // r, entry (u, tid) at ((u/2)*NT + tid)*2 + u%2
     __shared__ WavePart s_part[2][NW];
 
@@ -773,6 +774,42 @@ __device__ __forceinline__ void chain_tail(const ProblemView &P, double *__restr
         const int j = owned_col<NT, VEC>(u, tid);
         if (j < n) rg[j] = r[u];
     }
+}
+
+// The block-step chain of nsteps steps: chain_fast runs whole groups of
+// CHAIN_DA steps; a step it cannot take (a thread holding more than KA
+// support entries of the row) and the last nsteps % CHAIN_DA steps go
+// through chain_tail one at a time, after which chain_fast resumes with its
+// pipeline primed afresh.  Both leave r in global memory between calls, and
+// every chain_tail step ends with workgroup barriers, so the LDS of one
+// chain_fast call is free before the next one starts.  Returns the number
+// of steps taken by chain_tail.
+template <int NT, int CPT, int VEC, int COST, bool TRACE>
+__device__ __forceinline__ int64_t chain_run(const ProblemView &P, double *__restrict__ T,
+                                             double *__restrict__ rg, uint32_t *__restrict__ M,
+                                             const int32_t *__restrict__ idx, int64_t k0, int64_t nsteps,
+                                             int rule, int32_t *__restrict__ trace_j,
+                                             double *__restrict__ trace_gamma)
+{
+    int64_t start = 0, slow = 0;
+    while (start < nsteps) {
+        const int64_t rem = nsteps - start;
+        int64_t end = nsteps;
+        if (rem >= CHAIN_DA) {
+            const int64_t done = chain_fast<NT, CPT, VEC, COST, TRACE>(
+                P, T, rg, M, idx + start, k0 + start, rem, rule, TRACE ? trace_j + start : nullptr,
+                TRACE ? trace_gamma + start : nullptr);
+            start += done;
+            // a stop: one step without prefetch; else only the remainder is left
+            if (done != rem - rem % CHAIN_DA) end = start + 1;
+        }
+        if (start < end) {
+            chain_tail<NT, CPT, VEC, COST>(P, T, rg, M, idx, k0, start, end, rule, trace_j, trace_gamma);
+            slow += end - start;
+            start = end;
+        }
+    }
+    return slow;
 }
 
 // ---------------------------------------------------------------------------

@@ -50,7 +50,7 @@ struct DeviceState {
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
     int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW ticket
-    int64_t *resume;       // step at which the prefetching chain kernel stopped
+    int64_t *slow_steps;   // steps of the last chain launch taken without prefetch (diagnostic)
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
     double screen_delta2;  // 2 x error bound of the FP32 LMO screen (wide fused rows), 0 = unused
     double *ga_w;          // m, stored block gaps of the gap-adaptive sampler

@@ -47,24 +47,11 @@ __global__ __launch_bounds__(NT) void chain_kernel(ProblemView P, double *__rest
                                                    int64_t nsteps, int rule,
                                                    int32_t *__restrict__ trace_j,
                                                    double *__restrict__ trace_gamma,
-                                                   int64_t *__restrict__ resume)
+                                                   int64_t *__restrict__ slow_steps)
 {
-    const int64_t done = chain_fast<NT, CPT, VEC, COST, TRACE>(P, T, rg, M, idx, k0, nsteps, rule,
-                                                               trace_j, trace_gamma);
-    if (threadIdx.x == 0) *resume = done;
-}
-
-template <int NT, int CPT, int VEC, int COST>
-__global__ __launch_bounds__(NT) void chain_tail_kernel(ProblemView P, double *__restrict__ T,
-                                                        double *__restrict__ rg,
-                                                        uint32_t *__restrict__ M,
-                                                        const int32_t *__restrict__ idx, int64_t k0,
-                                                        int64_t nsteps, int rule,
-                                                        int32_t *__restrict__ trace_j,
-                                                        double *__restrict__ trace_gamma,
-                                                        const int64_t *__restrict__ resume)
-{
-    chain_tail<NT, CPT, VEC, COST>(P, T, rg, M, idx, k0, *resume, nsteps, rule, trace_j, trace_gamma);
+    const int64_t slow = chain_run<NT, CPT, VEC, COST, TRACE>(P, T, rg, M, idx, k0, nsteps, rule,
+                                                             trace_j, trace_gamma);
+    if (threadIdx.x == 0) *slow_steps = slow;
 }
 
 // ---------------------------------------------------------------------------
@@ -1266,15 +1253,11 @@ static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, 
         if (o.nt == NT_ && o.cpt == CPT_ && o.vec == VEC_) {                                       \
             if (tj || tg)                                                                          \
                 hipLaunchKernelGGL((chain_kernel<NT_, CPT_, VEC_, COST, true>), dim3(1), dim3(NT_), 0, \
-                                   st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.resume); \
+                                   st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.slow_steps); \
             else                                                                                   \
                 hipLaunchKernelGGL((chain_kernel<NT_, CPT_, VEC_, COST, false>), dim3(1), dim3(NT_),  \
                                    0, st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg,       \
-                                   S.resume);                                                      \
-            hipError_t e_ = hipGetLastError();                                                     \
-            if (e_ != hipSuccess) return e_;                                                       \
-            hipLaunchKernelGGL((chain_tail_kernel<NT_, CPT_, VEC_, COST>), dim3(1), dim3(NT_), 0,    \
-                               st, P, S.T, S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.resume);  \
+                                   S.slow_steps);                                                  \
             return hipGetLastError();                                                              \
         }
         SROT_VARIANTS_V1(SROT_CHAIN)
