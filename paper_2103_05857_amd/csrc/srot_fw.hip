@@ -32,19 +32,28 @@ __global__ __launch_bounds__(FW_NT) void fw_colsum_kernel(int32_t m, int32_t n, 
                                                           const int32_t *__restrict__ row_j,
                                                           int rows_per_slice, double *__restrict__ part)
 {
-    __shared__ int32_t sj[FW_NT];
-    __shared__ double sa[FW_NT];
+    __shared__ int4 sj[FW_NT / 4];
+    __shared__ double2 sa[FW_NT / 2];
     const int j = blockIdx.x * FW_NT + threadIdx.x;
     const int sl = blockIdx.y;
     const int i0 = sl * rows_per_slice, i1 = min(m, i0 + rows_per_slice);
     double acc = 0.0;
     for (int c0 = i0; c0 < i1; c0 += FW_NT) {
         const int i = c0 + threadIdx.x;
-        sj[threadIdx.x] = i < i1 ? row_j[i] : -1;
-        sa[threadIdx.x] = i < i1 ? a[i] : 0.0;
+        reinterpret_cast<int32_t *>(sj)[threadIdx.x] = i < i1 ? row_j[i] : -1;
+        reinterpret_cast<double *>(sa)[threadIdx.x] = i < i1 ? a[i] : 0.0;
         __syncthreads();
-        const int cnt = min(FW_NT, i1 - c0);
-        for (int k = 0; k < cnt; ++k) acc += (sj[k] == j) ? sa[k] : 0.0;
+        // rows in order, four at a time from 16-byte LDS reads (rows past
+        // the slice hold column -1 and add nothing)
+#pragma unroll 4
+        for (int k = 0; k < FW_NT / 4; ++k) {
+            const int4 q = sj[k];
+            const double2 x = sa[2 * k], y = sa[2 * k + 1];
+            acc += (q.x == j) ? x.x : 0.0;
+            acc += (q.y == j) ? x.y : 0.0;
+            acc += (q.z == j) ? y.x : 0.0;
+            acc += (q.w == j) ? y.y : 0.0;
+        }
         __syncthreads();
     }
     if (j < n) part[(size_t)sl * n + j] = acc;
@@ -67,8 +76,15 @@ __global__ __launch_bounds__(FW_NT) void fw_finish_kernel(int32_t n, const doubl
     const int j = blockIdx.x * FW_NT + threadIdx.x;
     double dd = 0.0;
     if (j < n) {
+        // slices in order; eight requested at a time
         double s = 0.0;
-        for (int sl = 0; sl < slices; ++sl) s += part[(size_t)sl * n + j];
+        for (int sl0 = 0; sl0 < slices; sl0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = (sl0 + q < slices) ? part[(size_t)(sl0 + q) * n + j] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += v[q];
+        }
         s_out[j] = s;
         const double d = (r[j] + b[j]) - s;
         dd = d * d;
