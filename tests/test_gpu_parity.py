@@ -161,7 +161,7 @@ def test_gap_sweep_on_given_plans(cost_mode, dtype):
     _need_gpu()
     rng = np.random.default_rng(3)
     shapes = [(1, 1, 1.0), (1, 9, 2.0), (17, 1, 0.5), (130, 257, 1.0), (64, 5003, 10.0),
-              (130, 256, 1.0), (64, 5004, 10.0), (6, 20000, 1.0)]
+              (3, 4, 1.0), (5, 8, 2.0), (130, 256, 1.0), (64, 5004, 10.0), (6, 20000, 1.0)]
     for (m, n, w) in shapes:
         d = I.problem_mixture(7, m, n, cost_dtype=dtype)
         T = rng.random((m, n)) * (rng.random((m, n)) < 0.05)
