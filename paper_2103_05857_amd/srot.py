@@ -132,8 +132,26 @@ def _check(status, allow=(SROT_OK,)):
     raise SrotError(status, f"{L.srot_strerror(status).decode()}: {L.srot_last_error().decode()}")
 
 
-def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+def _ptr(t, dtype=None, numel=0, pinned_ok=False):
+    """Device pointer of a contiguous CUDA tensor (or None).  The library
+    dereferences it on the GPU, so anything else is refused here: a host
+    pointer would fault the device."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise SrotError(SROT_EINVAL, f"expected a torch tensor, got {type(t).__name__}")
+    if not (t.is_cuda or (pinned_ok and t.is_pinned())):
+        raise SrotError(SROT_EINVAL, "expected a CUDA tensor" + (" or pinned host tensor" if pinned_ok else ""))
+    if not t.is_contiguous():
+        raise SrotError(SROT_EINVAL, "expected a contiguous tensor")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise SrotError(SROT_EINVAL, f"expected dtype {dtype}, got {t.dtype}")
+    if t.numel() < numel:
+        raise SrotError(SROT_EINVAL, f"tensor has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_F32, _F64, _I32 = torch.float32, torch.float64, torch.int32
 
 
 def _stream():
@@ -154,26 +172,29 @@ def srot_workspace_size(m, n, opt):
 
 def srot_init(m, n, C, X, Y, a, b, workspace, opt):
     h = ctypes.c_void_p()
-    _check(load().srot_init(ctypes.byref(h), m, n, _ptr(C), _ptr(X), _ptr(Y), _ptr(a), _ptr(b),
+    cdt = _F64 if opt.cost == SROT_COST_F64 else _F32
+    _check(load().srot_init(ctypes.byref(h), m, n, _ptr(C, cdt, m * n), _ptr(X, _F32, 3 * m), _ptr(Y, _F32, 3 * n),
+                            _ptr(a, _F64, m), _ptr(b, _F64, n),
                             _ptr(workspace), workspace.numel() * workspace.element_size(),
                             ctypes.byref(opt), _stream()))
     return h
 
 
 def srot_step(h, nsteps, idx=None, trace_j=None, trace_gamma=None):
-    _check(load().srot_step(h, nsteps, _ptr(idx), _ptr(trace_j), _ptr(trace_gamma)))
+    _check(load().srot_step(h, nsteps, _ptr(idx, _I32, nsteps), _ptr(trace_j, _I32, nsteps),
+                            _ptr(trace_gamma, _F64, nsteps)))
 
 
 def srot_gap(h, row_gap=None, row_argmin=None):
     out = (ctypes.c_double * 3)()
-    _check(load().srot_gap(h, out, _ptr(row_gap), _ptr(row_argmin)))
+    _check(load().srot_gap(h, out, _ptr(row_gap, _F64), _ptr(row_argmin, _I32)))
     return out[0], out[1], out[2]
 
 
 def srot_gap_async(h, out5):
     """Enqueues the gap sweep; out5 (5 doubles, device or pinned) receives
     {g, f, D, <T,C>, ||r||^2} when the stream gets there."""
-    _check(load().srot_gap_async(h, _ptr(out5)))
+    _check(load().srot_gap_async(h, _ptr(out5, _F64, 5, pinned_ok=True)))
 
 
 def srot_solve(h):
@@ -184,7 +205,7 @@ def srot_solve(h):
 
 
 def srot_get_plan(h, T_out=None, r_out=None):
-    _check(load().srot_get_plan(h, _ptr(T_out), _ptr(r_out)))
+    _check(load().srot_get_plan(h, _ptr(T_out, _F64), _ptr(r_out, _F64)))
 
 
 def srot_get_state(h):
@@ -194,15 +215,16 @@ def srot_get_state(h):
 
 
 def srot_set_state(h, T_in, k, r_in=None):
-    _check(load().srot_set_state(h, _ptr(T_in), _ptr(r_in), k))
+    _check(load().srot_set_state(h, _ptr(T_in, _F64), _ptr(r_in, _F64), k))
 
 
 def srot_backward(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):
-    _check(load().srot_backward(h, float(grad_out), _ptr(dC), _ptr(dX), _ptr(dY), _ptr(da), _ptr(db)))
+    _check(load().srot_backward(h, float(grad_out), _ptr(dC, (_F32, _F64)), _ptr(dX, _F32), _ptr(dY, _F32),
+                                _ptr(da, _F64), _ptr(db, _F64)))
 
 
 def srot_fw_steps(h, iters, trace_gamma=None):
-    _check(load().srot_fw_steps(h, int(iters), _ptr(trace_gamma)))
+    _check(load().srot_fw_steps(h, int(iters), _ptr(trace_gamma, _F64, iters)))
 
 
 def srot_fw_solve(h):
@@ -213,8 +235,9 @@ def srot_fw_solve(h):
 
 
 def srot_step_variant(h, variant, nsteps, idx=None, trace_j=None, trace_away=None, trace_gamma=None):
-    _check(load().srot_step_variant(h, int(variant), int(nsteps), _ptr(idx), _ptr(trace_j), _ptr(trace_away),
-                                    _ptr(trace_gamma)))
+    _check(load().srot_step_variant(h, int(variant), int(nsteps), _ptr(idx, _I32, nsteps),
+                                    _ptr(trace_j, _I32, nsteps), _ptr(trace_away, _I32, nsteps),
+                                    _ptr(trace_gamma, _F64, nsteps)))
 
 
 def srot_solve_variant(h, variant):
@@ -234,12 +257,13 @@ def srot_ga_refresh(h):
 
 
 def srot_ga_weights(h, W_out):
-    _check(load().srot_ga_weights(h, _ptr(W_out)))
+    _check(load().srot_ga_weights(h, _ptr(W_out, _F64)))
 
 
 def srot_step_ga(h, nsteps, u=None, trace_i=None, trace_j=None, trace_gamma=None, trace_g=None):
-    _check(load().srot_step_ga(h, int(nsteps), _ptr(u), _ptr(trace_i), _ptr(trace_j), _ptr(trace_gamma),
-                               _ptr(trace_g)))
+    _check(load().srot_step_ga(h, int(nsteps), _ptr(u, _F64, nsteps), _ptr(trace_i, _I32, nsteps),
+                               _ptr(trace_j, _I32, nsteps), _ptr(trace_gamma, _F64, nsteps),
+                               _ptr(trace_g, _F64, nsteps)))
 
 
 def srot_solve_ga(h, init=0.0, period=1):
@@ -251,7 +275,7 @@ def srot_solve_ga(h, init=0.0, period=1):
 
 
 def srot_barycentric(h, Xhat):
-    _check(load().srot_barycentric(h, _ptr(Xhat)))
+    _check(load().srot_barycentric(h, _ptr(Xhat, _F32)))
 
 
 def srot_destroy(h):
@@ -277,7 +301,7 @@ def srot_init_batched(m, n, c_off, C, a, b, workspace, opt, tune=0):
     c_off = None if c_off is None else np.ascontiguousarray(c_off, dtype=np.int64)
     h = ctypes.c_void_p()
     _check(load().srot_init_batched(ctypes.byref(h), len(m), _host_ptr(m), _host_ptr(n), _host_ptr(c_off),
-                                    _ptr(C), _ptr(a), _ptr(b), _ptr(workspace),
+                                    _ptr(C, _F32), _ptr(a, _F64), _ptr(b, _F64), _ptr(workspace),
                                     workspace.numel() * workspace.element_size(), ctypes.byref(opt),
                                     int(tune), _stream()))
     return h
@@ -294,7 +318,7 @@ def srot_solve_batched(h, count):
 
 
 def srot_get_plan_batched(h, p, T_out=None, r_out=None):
-    _check(load().srot_get_plan_batched(h, int(p), _ptr(T_out), _ptr(r_out)))
+    _check(load().srot_get_plan_batched(h, int(p), _ptr(T_out, _F64), _ptr(r_out, _F64)))
 
 
 def srot_get_tiles_batched(h, count):

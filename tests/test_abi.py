@@ -93,3 +93,18 @@ def test_null_handle_is_rejected():
     assert L.srot_ga_refresh(None) == S.SROT_EINVAL
     assert L.srot_ga_weights(None, None) == S.SROT_EINVAL
     assert L.srot_strerror(S.SROT_ENONFINITE) == b"non-finite or negative input"
+
+
+def test_binding_refuses_host_and_mistyped_tensors():
+    """Every tensor handed to the library is dereferenced on the GPU, so the
+    binding refuses host tensors, wrong dtypes, short and non-contiguous
+    tensors before any call reaches the library."""
+    import torch
+    from paper_2103_05857_amd import srot as S
+    with pytest.raises(S.SrotError):
+        S._ptr(torch.zeros(4, dtype=torch.int32))                 # host memory
+    with pytest.raises(S.SrotError):
+        S.srot_step(None, 4, torch.zeros(4, dtype=torch.int32))
+    with pytest.raises(S.SrotError):
+        S._ptr([1, 2, 3])
+    assert S._ptr(None) is None
