@@ -400,3 +400,42 @@ def test_full_size_4096_first_passes_and_solve_properties():
     st2.T = st.T.copy(); st2.r = st.r.copy(); st2.k = st.k
     _, hist = O.solve(P, lambda p: src(p + 2), eps=1e-6, max_passes=200, state=st2)
     assert abs(f - hist[-1]["f"]) <= g + hist[-1]["g"] + 1e-12
+
+
+def test_full_size_fused_32768_sampled_rows_and_invariants():
+    """m = n = 32768 mixture points, fused cost, b ~ Dirichlet(1), w = 1, in
+    the benchmark's launch configuration (one srot_step of m block steps per
+    pass).  The dense FP64 oracle does not fit at this size, so after one
+    pass the sweep's per-row outputs are checked on sampled rows against an
+    FP64 evaluation of those rows (gradient minimum, vertex up to ties, row
+    gap), and the plan against invariants that hold at any size: T >= 0,
+    row sums a, r = T^T 1 - b, g = sum_i g_i."""
+    _need_gpu()
+    n = m = 32768
+    w = 1.0
+    d = I.problem_mixture(0, m, n, dirichlet_b=True, with_cost=False)
+    sol = _gpu_problem(d, "sqeuclid", w, seed=0)
+    sol.step(m)
+    (g, f, D), rg, rj = sol.gap(per_row=True)
+    T, r = sol.plan()
+    b = torch.from_numpy(d["b"]).to(DEV)
+    a = torch.from_numpy(d["a"]).to(DEV)
+    assert T.min().item() >= 0.0
+    torch.testing.assert_close(T.sum(dim=1), a, rtol=1e-12, atol=0.0)
+    torch.testing.assert_close(r, T.sum(dim=0) - b, rtol=0.0, atol=1e-12)
+    rg = rg.cpu().numpy()
+    assert abs(g - rg.sum()) <= 1e-9 * abs(g)
+    assert abs((f - D) - g) <= 1e-9 * max(abs(f), 1e-12)
+    rows = np.random.default_rng(4).choice(m, 64, replace=False)
+    rn = r.cpu().numpy()
+    X = d["X"].astype(np.float64)
+    Y = d["Y"].astype(np.float64)
+    rjn = rj.cpu().numpy()
+    Tr = T[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    for q, i in enumerate(rows):
+        v = ((X[i][None, :] - Y) ** 2).sum(axis=1) + w * rn
+        G = v.min()
+        assert v[rjn[i]] - G <= 1e-12 * max(1.0, abs(G))
+        gi = float(np.sum(Tr[q] * (v - G)))
+        assert abs(rg[i] - gi) <= 1e-9 * max(gi, 1e-12) + 1e-15
+    sol.close()
