@@ -141,3 +141,40 @@ def test_batched_error_paths():
     with pytest.raises(S.SrotError) as e:
         S.srot_init_batched([4, 4], [4, 4], None, C, a, a, ws, opt)
     assert e.value.status == S.SROT_ENOMEM
+
+
+def test_full_size_512_problems_autotuned():
+    """The 512-problem workload (m, n log-uniform in [64, 4096], mixture
+    palettes, FP32 costs, w = 1, gap 1e-6) in the benchmark's launch
+    configuration (one graph launch, autotuned tiles): every problem reaches
+    its gap, and sampled problems agree with the single-problem solver
+    within the two gaps and satisfy the plan invariants."""
+    S = _S()
+    count = 512
+    ms, ns = I.batched_sizes(0, count)
+    probs = [I.batched_problem(0, p, int(ms[p]), int(ns[p])) for p in range(count)]
+    opts = dict(w=1.0, eps=1e-6, max_passes=20000, seed=0)
+    Cs = []
+    for d in probs:   # squared Euclidean in FP64 on the device, stored in FP32
+        X = torch.from_numpy(d["X"]).to(DEV).double()
+        Y = torch.from_numpy(d["Y"]).to(DEV).double()
+        Cs.append(((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1).float().contiguous())
+    As = [torch.from_numpy(d["a"]).to(DEV) for d in probs]
+    Bs = [torch.from_numpy(d["b"]).to(DEV) for d in probs]
+    bs = S.BatchSolver(Cs, As, Bs, tune=True, **opts)
+    st, out3, passes, status = bs.solve()
+    assert np.all(status == S.SROT_OK) and np.all(out3[:, 0] <= 1e-6)
+    assert np.allclose(out3[:, 1] - out3[:, 2], out3[:, 0], rtol=1e-9, atol=1e-15)
+    small = [p for p in range(count) if ms[p] * ns[p] <= 300_000]
+    for p in np.random.default_rng(1).choice(small, 6, replace=False):
+        sol = S.Solver(As[p], Bs[p], C=Cs[p], **opts)
+        s1, (g, f, D), _ = sol.solve()
+        sol.close()
+        assert s1 == S.SROT_OK
+        assert abs(out3[p, 1] - f) <= out3[p, 0] + g + 1e-15
+        T, r = bs.plan(int(p))
+        Th = T.cpu().numpy()
+        assert Th.min() >= 0.0
+        np.testing.assert_allclose(Th.sum(axis=1), probs[p]["a"], rtol=1e-12)
+        np.testing.assert_allclose(r.cpu().numpy(), Th.sum(axis=0) - probs[p]["b"], rtol=0, atol=1e-13)
+    bs.close()
