@@ -172,7 +172,7 @@ __global__ __launch_bounds__(GLB_NT) void chain_glb_kernel(ProblemView P, double
 constexpr int WIDE_NT = 512;
 constexpr int WIDE_KA = 2;
 constexpr int WIDE_MAX_N = WIDE_NT * 64;
-constexpr int WIDE_B = 8;  // columns per streamed batch  // support entries per thread read ahead of the screen
+constexpr int WIDE_B = 16;  // columns per streamed batch of target points
 
 __device__ __forceinline__ float wave_min_f32(float v)
 {
@@ -228,6 +228,22 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
         }
         r32[j] = (j < n) ? (float)rg[j] : 0.0f;
     }
+
+    // YMODE 0: the thread's points are streamed in batches of WIDE_B
+    // columns, double buffered; the batches repeat every step (the points do
+    // not depend on the row), so the last batch of a step requests the
+    // first batch of the next one.
+    constexpr int YB = YMODE == 0 ? WIDE_B : 1;
+    static_assert(YMODE == 1 || CPTK % (2 * WIDE_B) == 0, "whole pairs of batches");
+    float4 ya[YB], yb2[YB];
+    auto issue_batch = [&](float4 (&q)[YB], int ub) {
+#pragma unroll
+        for (int e = 0; e < YB; ++e) {
+            const int j = (ub + e) * WIDE_NT + tid;
+            q[e] = Y4[j < n ? j : n - 1];
+        }
+    };
+    if constexpr (YMODE == 0) issue_batch(ya, 0);
 
     // row data of the next step (index, point, weight, this thread's mask
     // words) is requested one step ahead; a mask is forwarded when the next
@@ -294,25 +310,30 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
                 __builtin_amdgcn_sched_barrier(0);  // the point registers stay the only per-column state
             }
         } else {
-            // points streamed from L2, WIDE_B columns per batch
-#pragma unroll 1
-            for (int ub = 0; ub < CPTK; ub += WIDE_B) {
-                float q0[WIDE_B], q1[WIDE_B], q2[WIDE_B];
+            auto consume = [&](const float4 (&q)[YB], int ub) {
 #pragma unroll
-                for (int e = 0; e < WIDE_B; ++e) {
-                    const int j = (ub + e) * WIDE_NT + tid;
-                    const float *yp = P.Y + 3 * (j < n ? j : n - 1);
-                    const bool real = j < n;
-                    q0[e] = real ? yp[0] : 3e18f;
-                    q1[e] = real ? yp[1] : 3e18f;
-                    q2[e] = real ? yp[2] : 3e18f;
-                }
-#pragma unroll
-                for (int e = 0; e < WIDE_B; ++e) {
-                    const float d0 = x0 - q0[e], d1 = x1 - q1[e], d2 = x2 - q2[e];
+                for (int e = 0; e < YB; ++e) {
+                    const bool real = (ub + e) * WIDE_NT + tid < n;
+                    const float d0 = x0 - (real ? q[e].x : 3e18f);
+                    const float d1 = x1 - (real ? q[e].y : 3e18f);
+                    const float d2 = x2 - (real ? q[e].z : 3e18f);
                     const float c = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
                     screen(ub + e, fmaf(w32, r32[(ub + e) * WIDE_NT + tid], c));
                 }
+            };
+            // one pair of batches per iteration; the scheduling barriers keep
+            // each batch's loads one batch ahead of its use (hoisting them all
+            // would need registers for every point of the step)
+#pragma unroll 1
+            for (int ub = 0; ub < CPTK; ub += 2 * WIDE_B) {
+                issue_batch(yb2, ub + WIDE_B);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(ya, ub);
+                __builtin_amdgcn_sched_barrier(0);
+                issue_batch(ya, (ub + 2 * WIDE_B) % CPTK);
+                __builtin_amdgcn_sched_barrier(0);
+                consume(yb2, ub + WIDE_B);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         const int j1 = u1 * WIDE_NT + tid;
