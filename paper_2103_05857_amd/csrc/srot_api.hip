@@ -92,7 +92,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.slow = off; off = align_up(off + sizeof(int64_t));
-    L.Y4 = off; off = align_up(off + 16 * (size_t)n);
+    L.Y4 = off; off = align_up(off + 16 * ((size_t)n + 1));  // + sentinel point
     L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
     L.ga_w = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.total = off;

@@ -14,7 +14,7 @@ struct ProblemView {
     const void *C;         // m x n (float or double), or nullptr
     const float *X;        // m x 3
     const float *Y;        // n x 3
-    const float4 *Y4;      // n, Y padded to 16 bytes (workspace), or nullptr
+    const float4 *Y4;      // n + 1: Y padded to 16 bytes and a sentinel point (workspace), or nullptr
     const double *a;       // m
     const double *b;       // n
     double w;

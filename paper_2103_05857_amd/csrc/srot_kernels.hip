@@ -240,7 +240,7 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
 #pragma unroll
         for (int e = 0; e < YB; ++e) {
             const int j = (ub + e) * WIDE_NT + tid;
-            q[e] = Y4[j < n ? j : n - 1];
+            q[e] = Y4[j < n ? j : n];  // Y4[n]: the sentinel point
         }
     };
     if constexpr (YMODE == 0) issue_batch(ya, 0);
@@ -295,11 +295,13 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
         // stage 1: FP32 screen, smallest and second smallest value per thread
         float b1 = INFINITY, b2 = INFINITY;
         int u1 = 0;
+        // running smallest (b1, at column u1; ties keep the lower column) and
+        // second smallest b2: with b1 <= b2 the median of {b1, b2, v} is the
+        // new second smallest
         auto screen = [&](int u, float v) {
-            const bool lt = v < b1;
-            b2 = lt ? b1 : fminf(b2, v);
-            u1 = lt ? u : u1;
-            b1 = lt ? v : b1;
+            u1 = (v < b1) ? u : u1;
+            b2 = __builtin_amdgcn_fmed3f(b1, b2, v);
+            b1 = fminf(b1, v);
         };
         if constexpr (YMODE == 1) {
 #pragma unroll
@@ -311,14 +313,15 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
             }
         } else {
             auto consume = [&](const float4 (&q)[YB], int ub) {
+                const float *rb = r32 + ub * WIDE_NT + tid;
+                float rr[YB];
+#pragma unroll
+                for (int e = 0; e < YB; ++e) rr[e] = rb[e * WIDE_NT];
 #pragma unroll
                 for (int e = 0; e < YB; ++e) {
-                    const bool real = (ub + e) * WIDE_NT + tid < n;
-                    const float d0 = x0 - (real ? q[e].x : 3e18f);
-                    const float d1 = x1 - (real ? q[e].y : 3e18f);
-                    const float d2 = x2 - (real ? q[e].z : 3e18f);
+                    const float d0 = x0 - q[e].x, d1 = x1 - q[e].y, d2 = x2 - q[e].z;
                     const float c = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
-                    screen(ub + e, fmaf(w32, r32[(ub + e) * WIDE_NT + tid], c));
+                    screen(ub + e, fmaf(w32, rr[e], c));
                 }
             };
             // one pair of batches per iteration; the scheduling barriers keep
@@ -1020,11 +1023,13 @@ __global__ void init_plan_kernel(int32_t m, int32_t n, const double *__restrict_
     }
 }
 
-// Target points padded to 16 bytes (one vector load per point).
+// Target points padded to 16 bytes (one vector load per point), followed by
+// a sentinel point at index n, 3e18 away from every coordinate: a streamed
+// screen reads it for columns past n - 1 instead of selecting per column.
 __global__ void pad_points_kernel(int32_t n, const float *__restrict__ Y, float4 *__restrict__ Y4)
 {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
-        Y4[j] = make_float4(Y[3 * j], Y[3 * j + 1], Y[3 * j + 2], 0.f);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j <= n; j += gridDim.x * blockDim.x)
+        Y4[j] = (j < n) ? make_float4(Y[3 * j], Y[3 * j + 1], Y[3 * j + 2], 0.f) : make_float4(3e18f, 3e18f, 3e18f, 0.f);
 }
 
 // r_j = sum_i T_ij - b_j, rows added in order.
