@@ -92,7 +92,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.slow = off; off = align_up(off + sizeof(int64_t));
-    L.Y4 = off; off = align_up(off + 16 * ((size_t)n + 1));  // + sentinel point
+    L.Y4 = off; off = align_up(off + 16 * (size_t)srot::y4_entries(n));
     L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
     L.ga_w = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.total = off;
@@ -262,6 +262,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->P.w = opt->w;
     char *base = (char *)workspace;
     h->P.Y4 = Y ? (const float4 *)(base + L.Y4) : nullptr;
+    h->P.y4n = (int32_t)srot::y4_entries(n);
     h->S.T = (double *)(base + L.T);
     h->S.r = (double *)(base + L.r);
     h->S.mask = (uint32_t *)(base + L.mask);

@@ -14,7 +14,8 @@ struct ProblemView {
     const void *C;         // m x n (float or double), or nullptr
     const float *X;        // m x 3
     const float *Y;        // n x 3
-    const float4 *Y4;      // n + 1: Y padded to 16 bytes and a sentinel point (workspace), or nullptr
+    const float4 *Y4;      // y4n entries: Y padded to 16 bytes, then sentinel points (workspace), or nullptr
+    int32_t y4n;           // entries of Y4 (y4_entries(n))
     const double *a;       // m
     const double *b;       // n
     double w;
@@ -84,6 +85,17 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream);
 // {squared diameter of the points' bounding box, max(sum a, max b)} into out2.
 hipError_t launch_screen_bounds(const ProblemView &P, double *out2, hipStream_t stream);
+
+// Entries of the padded target points: n real points followed by sentinel
+// points, at least one, and up to the columns the wide-row chain touches
+// (8192, 16384 or 32768 when n exceeds 4096).
+inline int64_t y4_entries(int64_t n)
+{
+    if (n <= 4096) return n + 1;
+    int64_t cols = 8192;
+    while (cols < n) cols *= 2;
+    return cols > n ? cols : n + 1;
+}
 
 // Number of workgroups used by the gap sweep for an m-row problem.
 int32_t gap_blocks_for(int64_t m);

@@ -236,12 +236,14 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
     constexpr int YB = YMODE == 0 ? WIDE_B : 1;
     static_assert(YMODE == 1 || CPTK % (2 * WIDE_B) == 0, "whole pairs of batches");
     float4 ya[YB], yb2[YB];
+    // raw buffer loads: the lane's offset in a vector register, the batch's
+    // column offset in a scalar one; entries past n hold sentinel points
+    const __amdgpu_buffer_rsrc_t rs_y = buf_rsrc(Y4, (unsigned)P.y4n * 16u);
     auto issue_batch = [&](float4 (&q)[YB], int ub) {
 #pragma unroll
-        for (int e = 0; e < YB; ++e) {
-            const int j = (ub + e) * WIDE_NT + tid;
-            q[e] = Y4[j < n ? j : n];  // Y4[n]: the sentinel point
-        }
+        for (int e = 0; e < YB; ++e)
+            q[e] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                  rs_y, tid * 16, (ub + e) * WIDE_NT * 16, 0));
     };
     if constexpr (YMODE == 0) issue_batch(ya, 0);
 
@@ -1024,11 +1026,12 @@ __global__ void init_plan_kernel(int32_t m, int32_t n, const double *__restrict_
 }
 
 // Target points padded to 16 bytes (one vector load per point), followed by
-// a sentinel point at index n, 3e18 away from every coordinate: a streamed
-// screen reads it for columns past n - 1 instead of selecting per column.
-__global__ void pad_points_kernel(int32_t n, const float *__restrict__ Y, float4 *__restrict__ Y4)
+// sentinel points 3e18 away from every coordinate up to entry y4n - 1: a
+// streamed screen reads them for columns past n - 1 instead of selecting
+// per column.
+__global__ void pad_points_kernel(int32_t n, int32_t y4n, const float *__restrict__ Y, float4 *__restrict__ Y4)
 {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j <= n; j += gridDim.x * blockDim.x)
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < y4n; j += gridDim.x * blockDim.x)
         Y4[j] = (j < n) ? make_float4(Y[3 * j], Y[3 * j + 1], Y[3 * j + 2], 0.f) : make_float4(3e18f, 3e18f, 3e18f, 0.f);
 }
 
@@ -1239,8 +1242,8 @@ hipError_t launch_residual(const ProblemView &P, const DeviceState &S, hipStream
 hipError_t launch_pad_points(const ProblemView &P, hipStream_t stream)
 {
     if (!P.Y || !P.Y4) return hipSuccess;
-    hipLaunchKernelGGL(pad_points_kernel, dim3(grid_for((size_t)P.n, 256, 1024)), dim3(256), 0, stream,
-                       P.n, P.Y, const_cast<float4 *>(P.Y4));
+    hipLaunchKernelGGL(pad_points_kernel, dim3(grid_for((size_t)P.y4n, 256, 1024)), dim3(256), 0, stream,
+                       P.n, P.y4n, P.Y, const_cast<float4 *>(P.Y4));
     return hipGetLastError();
 }
 
