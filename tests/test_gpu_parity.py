@@ -13,7 +13,7 @@ and is widened exactly):
     on the atoms of the row it moves, so such ties recur by construction;
   * step sizes within 1e-9 absolute;
   * per-pass objective f within 1e-6 relative and gap g within
-    1e-6 * max(g, 1e-9) + 1e-15 (the benchmark spec's tolerance, with an absolute
+    1e-6 * max(g, 1e-9) + 1e-15 (the stated 1e-6 relative tolerance, with an absolute
     floor for FP64 rounding of a tiny difference).
 """
 import numpy as np
