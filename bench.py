@@ -281,19 +281,21 @@ def bench_fw(args, C, a, b):
 
 def bench_variants(args, C, a, b):
     """Time to gap 1e-6 from the initial plan on the stored-cost workload
-    (w = 1, uniform sampling, gap every pass): plain BCFW (Alg. 1) against
-    the away-step (Alg. A.2) and pairwise (Alg. A.3) block steps, gap-adaptive
-    sampling (Alg. A.4, global update every pass) and full FW (Alg. A.1, gap
-    at every iteration; "passes" counts its iterations)."""
+    (w = 1, gap every pass): plain BCFW (Alg. 1) with uniform and with
+    per-pass permutation sampling, the away-step (Alg. A.2) and pairwise
+    (Alg. A.3) block steps, gap-adaptive sampling (Alg. A.4, global update
+    every pass) and full FW (Alg. A.1, gap at every iteration; "passes"
+    counts its iterations)."""
     import torch
     from paper_2103_05857_amd import srot as S
     out = {}
-    for name, variant in (("bcfw", None), ("away", S.SROT_STEP_AWAY), ("pairwise", S.SROT_STEP_PAIRWISE),
-                          ("gap_adaptive", "ga"), ("full_fw", "fw")):
-        sol = S.Solver(a, b, C=C, w=1.0, seed=0, eps=1e-6, max_passes=2000)
+    for name, variant in (("bcfw", None), ("bcfw_permutation", "perm"), ("away", S.SROT_STEP_AWAY),
+                          ("pairwise", S.SROT_STEP_PAIRWISE), ("gap_adaptive", "ga"), ("full_fw", "fw")):
+        sampling = S.SROT_PERMUTE if variant == "perm" else S.SROT_UNIFORM
+        sol = S.Solver(a, b, C=C, w=1.0, seed=0, eps=1e-6, max_passes=2000, sampling=sampling)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if variant is None:
+        if variant is None or variant == "perm":
             st, (g, f, D), passes = sol.solve()
         elif variant == "fw":
             st, (g, f, D), passes = S.srot_fw_solve(sol.h)    # passes = FW iterations
