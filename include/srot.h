@@ -164,6 +164,22 @@ int srot_get_plan(srot_handle *h, double *T_out, double *r_out);
 int srot_get_state(srot_handle *h, int64_t *k);
 int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64_t k);
 
+/* Diagnostics of the last block-step launch (srot_step, or the steps of a
+ * pass of srot_solve), written to out4 (host, 4 int64; synchronises):
+ *   out4[0]  steps whose LMO (eq. SemiRelaxedSubproblemImplement) scanned the
+ *            full row outside the chain's fast path: with the screened LMO
+ *            (stored FP32 cost, 1025-4096 columns), steps where the
+ *            candidates could not be certified; otherwise steps taken by the
+ *            one-at-a-time tail path;
+ *   out4[1]  screened LMO only: steps whose support was re-read from the plan
+ *            (rows updated within the last 8 steps, or rows with more
+ *            nonzeros per screener lane than prepared);
+ *   out4[2], out4[3]  0 (reserved).
+ * Neither changes any result: every path takes the same exact step.
+ * Setting SROT_LMO_SCREEN=0 in the environment before srot_init selects the
+ * unscreened chain for that handle. */
+int srot_chain_stats(srot_handle *h, int64_t *out4);
+
 /* Gradients of the optimal value V = min f (the problem above) with respect
  * to the inputs, evaluated at the handle's current plan T and scaled by
  * grad_out (dL/dV of a caller's loss L).  The paper does not differentiate

@@ -91,7 +91,7 @@ Layout make_layout(int64_t m, int64_t n)
     off = align_up(off + sizeof(double) * std::max<size_t>(8 * (size_t)L.gap_blocks, (size_t)srot::fw_finish_blocks(n)));
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
-    L.slow = off; off = align_up(off + sizeof(int64_t));
+    L.slow = off; off = align_up(off + 4 * sizeof(int64_t));
     L.Y4 = off; off = align_up(off + 16 * (size_t)srot::y4_entries(n));
     L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
     L.ga_w = off; off = align_up(off + sizeof(double) * (size_t)m);
@@ -283,6 +283,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     int rc = SROT_OK;
     int32_t flag = 0;
     hipError_t e = hipMemsetAsync(h->S.flags, 0, sizeof(int32_t) * 8, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->S.slow_steps, 0, sizeof(int64_t) * 4, h->stream);
     if (e == hipSuccess) e = srot::launch_validate(h->P, h->S, h->stream);
     if (e == hipSuccess) e = srot::launch_pad_points(h->P, h->stream);
     if (e == hipSuccess) e = srot::launch_init_plan(h->P, h->S, h->stream);
@@ -292,15 +293,26 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     // the FP32 LMO screen of wide fused rows needs an error bound (see the
     // wide-row chain kernel): 8 u (Cmax + |w| Rmax), doubled, u = 2^-24
     const bool wide = opt->cost == SROT_COST_SQEUCLID && !h->S.own.reg;
+    // the screened chain's FP32 LMO screen needs the same kind of bound on
+    // the stored cost: max |c_ij| and max(sum a, max b)
+    const bool screened = srot::screened_chain_supported(h->P, h->S) && srot::screened_chain_enabled();
     double bounds[2] = {0.0, 0.0};
     if (e == hipSuccess && wide) e = srot::launch_screen_bounds(h->P, h->S.scalars + 5, h->stream);
-    if (e == hipSuccess && wide)
+    if (e == hipSuccess && screened) e = srot::launch_cost_bounds(h->P, h->S, h->S.scalars + 5, h->stream);
+    if (e == hipSuccess && (wide || screened))
         e = hipMemcpyAsync(bounds, h->S.scalars + 5, sizeof(bounds), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init: %s", hipGetErrorString(e));
     else if (flag & 1) rc = fail(SROT_ENONFINITE, "srot_init: NaN/Inf in C, X, Y, a or b, or a negative weight");
     h->S.screen_delta2 = 0.0;
+    h->S.screen_err = 0.0;
+    if (rc == SROT_OK && screened) {
+        // FP32 screen value fma(w, r, c) against c + w r: at most 2^-22
+        // (|c| + |w| |r|) off (rounding of r, w and the fma); doubled
+        const double scale = bounds[0] + fabs(opt->w) * bounds[1];
+        h->S.screen_err = 0x1.0p-21 * scale * (1.0 + 1e-6) + 1e-300;
+    }
     if (rc == SROT_OK && wide) {
         const double u = 0x1.0p-24;
         const double scale = bounds[0] + fabs(opt->w) * bounds[1];
@@ -389,6 +401,14 @@ int srot_get_state(srot_handle *h, int64_t *k)
 {
     if (!h || !k) return fail(SROT_EINVAL, "srot_get_state: NULL argument");
     *k = h->k;
+    return SROT_OK;
+}
+
+int srot_chain_stats(srot_handle *h, int64_t *out4)
+{
+    if (!h || !out4) return fail(SROT_EINVAL, "srot_chain_stats: NULL argument");
+    SROT_HIP(hipMemcpyAsync(out4, h->S.slow_steps, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, h->stream));
+    SROT_HIP(hipStreamSynchronize(h->stream));
     return SROT_OK;
 }
 

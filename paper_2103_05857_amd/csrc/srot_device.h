@@ -624,8 +624,9 @@ __device__ __forceinline__ int64_t chain_fast(const ProblemView &P, double *__re
             }
             buf_store_u32(nm, buf_rsrc(M + (size_t)i * NT, NT * 4u), nm != mk ? (unsigned)tid * 4u : kOOB);
             if constexpr (TRACE) {
-                const __amdgpu_buffer_rsrc_t rs_tj = buf_rsrc(trace_j, (unsigned)nsteps * 4u);
-                const __amdgpu_buffer_rsrc_t rs_tg = buf_rsrc(trace_gamma, (unsigned)nsteps * 8u);
+                // a null trace pointer gets an empty range: its stores are dropped
+                const __amdgpu_buffer_rsrc_t rs_tj = buf_rsrc(trace_j, trace_j ? (unsigned)nsteps * 4u : 0u);
+                const __amdgpu_buffer_rsrc_t rs_tg = buf_rsrc(trace_gamma, trace_gamma ? (unsigned)nsteps * 8u : 0u);
                 buf_store_u32((unsigned)jstar, rs_tj, tid == 0 ? (unsigned)s * 4u : kOOB);
                 buf_store_f64(gamma, rs_tg, tid == 0 ? (unsigned)s * 8u : kOOB);
             }

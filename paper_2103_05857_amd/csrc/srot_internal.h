@@ -51,9 +51,10 @@ struct DeviceState {
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
     int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW ticket
-    int64_t *slow_steps;   // steps of the last chain launch taken without prefetch (diagnostic)
+    int64_t *slow_steps;   // 4: slow-path step counts of the last chain launch (diagnostic)
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
     double screen_delta2;  // 2 x error bound of the FP32 LMO screen (wide fused rows), 0 = unused
+    double screen_err;     // error bound of the FP32 LMO screen of the screened chain, 0 = chain unused
     double *ga_w;          // m, stored block gaps of the gap-adaptive sampler
 };
 
@@ -83,6 +84,17 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
                         int64_t k0, int64_t nsteps, int rule, int32_t *trace_j,
                         double *trace_gamma, hipStream_t stream);
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+
+// Screened-LMO chain (srot_screen.hip): stored FP32 cost in the 256 x {8,16}
+// x 4 ownership.  launch_cost_bounds writes {max |c_ij|, max(sum a, max b)}
+// to out2 (device; uses the gap partial buffer); the chain needs
+// S.screen_err > 0.  SROT_LMO_SCREEN=0 in the environment turns it off.
+bool screened_chain_supported(const ProblemView &P, const DeviceState &S);
+bool screened_chain_enabled();
+hipError_t launch_cost_bounds(const ProblemView &P, const DeviceState &S, double *out2, hipStream_t stream);
+hipError_t launch_chain_screened(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t k0,
+                                 int64_t nsteps, int rule, int32_t *trace_j, double *trace_gamma,
+                                 hipStream_t stream);
 // {squared diameter of the points' bounding box, max(sum a, max b)} into out2.
 hipError_t launch_screen_bounds(const ProblemView &P, double *out2, hipStream_t stream);
 

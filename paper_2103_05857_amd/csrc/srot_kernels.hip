@@ -1277,6 +1277,10 @@ static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, 
                                     hipStream_t st)
 {
     const Ownership &o = S.own;
+    if constexpr (COST == SROT_COST_F32) {
+        if (S.screen_err > 0.0 && screened_chain_supported(P, S))
+            return launch_chain_screened(P, S, idx, k0, nsteps, rule, tj, tg, st);
+    }
     if (o.reg) {
 #define SROT_CHAIN(NT_, CPT_, VEC_)                                                                \
         if (o.nt == NT_ && o.cpt == CPT_ && o.vec == VEC_) {                                       \

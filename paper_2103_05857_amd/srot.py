@@ -80,6 +80,8 @@ def load():
     L.srot_get_state.restype = ctypes.c_int
     L.srot_set_state.argtypes = [_vp, _vp, _vp, _i64]
     L.srot_set_state.restype = ctypes.c_int
+    L.srot_chain_stats.argtypes = [_vp, _vp]
+    L.srot_chain_stats.restype = ctypes.c_int
     L.srot_backward.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
     L.srot_backward.restype = ctypes.c_int
     L.srot_workspace_size_batched.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.POINTER(srot_options)]
@@ -216,6 +218,12 @@ def srot_get_state(h):
 
 def srot_set_state(h, T_in, k, r_in=None):
     _check(load().srot_set_state(h, _ptr(T_in, _F64), _ptr(r_in, _F64), k))
+
+
+def srot_chain_stats(h):
+    out = (ctypes.c_int64 * 4)()
+    _check(load().srot_chain_stats(h, out))
+    return list(out)
 
 
 def srot_backward(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):

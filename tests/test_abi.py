@@ -92,6 +92,8 @@ def test_null_handle_is_rejected():
     assert L.srot_ga_reset(None, 1.0) == S.SROT_EINVAL
     assert L.srot_ga_refresh(None) == S.SROT_EINVAL
     assert L.srot_ga_weights(None, None) == S.SROT_EINVAL
+    stats = (ctypes.c_int64 * 4)()
+    assert L.srot_chain_stats(None, stats) == S.SROT_EINVAL
     assert L.srot_strerror(S.SROT_ENONFINITE) == b"non-finite or negative input"
 
 
