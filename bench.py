@@ -23,7 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS_SRC = [os.path.join(ROOT, "paper_2103_05857_amd", "csrc", f) for f in ("srot_kernels.hip", "srot_device.h")]
+KERNELS_SRC = [os.path.join(ROOT, "paper_2103_05857_amd", "csrc", f)
+               for f in ("srot_kernels.hip", "srot_device.h", "srot_screen.hip")]
 PROFILE = os.path.join(ROOT, "profiles", "chain_gap_stored_f32_m4096_n4096.md")
 SWEEP_PROFILE = os.path.join(ROOT, "profiles", "gap_sweep_stored_f32_m16384_n16384.md")
 
@@ -95,6 +96,7 @@ def main():
     chain_ms = []          # event-timed srot_step(m) launches (sample + chain kernel)
     gap_ms = []            # event-timed gap sweeps (gap kernel + final reduction)
     nnz_rows = []
+    screen_stats = {}
     ttg = {}
     for w in weights:
         sol = S.Solver(a, b, C=C, w=w, seed=0, eps=1e-6, max_passes=1, gap_every=1)
@@ -122,6 +124,8 @@ def main():
         total_s += dt
         chain_ms += [e0.elapsed_time(e1) for e0, e1 in ev]
         gap_ms += [ev[p][1].elapsed_time(evg[p]) for p in range(args.steps)]
+        st = S.srot_chain_stats(sol.h)      # the last timed pass
+        screen_stats[str(w)] = dict(full_row_lmo=st[0], support_reread=st[1], steps=m)
         T, _ = sol.plan()
         nnz_rows.append(float((T > 0).sum().item()) / m)
         sol.close()
@@ -145,8 +149,8 @@ def main():
     nnz = float(np.mean(nnz_rows))
     bytes_per_step = 4.0 * n + 24.0 * (nnz + 1.0)
     achieved = bytes_per_step * m / (chain_avg_ms * 1e-3) / 1e9
-    traffic = counter_traffic("srot::chain_kernel<256, 16, 4, 0, false>")
-    roofline = dict(kernel="chain_kernel<256,16,4,f32>", bound="hbm", achieved=achieved,
+    traffic = counter_traffic("srot::chain_screened_kernel<16, false>")
+    roofline = dict(kernel="chain_screened_kernel<16,f32>", bound="hbm", achieved=achieved,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, bytes_per_launch=bytes_per_step * m, launch_ms=chain_avg_ms,
                     us_per_block_update=1000.0 * chain_avg_ms / m)
@@ -180,6 +184,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_gap_1e-6": ttg,
         "mean_row_nnz": nnz,
+        "screened_lmo_last_pass": screen_stats,
     }
     sections = [x for x in args.sections.split(",") if x]
     if "sweep" in sections:

@@ -1,15 +1,20 @@
 """Batched solver (srot_init_batched / srot_solve_batched) on the GPU.
 
 * With the default tile shapes every problem follows exactly the trajectory
-  of the single-problem solver (same chain code, same tile shape, same
-  Philox block-index stream): plans and residuals must be bit-identical and
-  the stop pass the same; the gap certificates (g, f, D) agree to FP64
-  rounding (the batched sweep sums rows in another order).
+  of the single-problem solver run with the same (prefetching) chain code
+  (same tile shape, same Philox block-index stream; the single-problem
+  handles are created with SROT_LMO_SCREEN=0, since the screened-LMO chain
+  takes the same steps but sums the line-search partials in another order):
+  plans and residuals must be bit-identical and the stop pass the same; the
+  gap certificates (g, f, D) agree to FP64 rounding (the batched sweep sums
+  rows in another order).
 * Against the FP64 oracle directly: per-problem f and g after the passes the
   batched solver ran, under the parity bar of the single-problem tests.
 * With autotuned tile shapes every problem still converges to the same
   optimum: f within 1e-6 relative of the single-problem solver's, g <= eps.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -55,8 +60,12 @@ def test_batched_equals_single_problem_solver_bitwise():
     st, out3, passes, status = bs.solve()
     tiles, _ = bs.tiles()
     for p, d in enumerate(probs):
-        sol = S.Solver(torch.from_numpy(d["a"]).to(DEV), torch.from_numpy(d["b"]).to(DEV),
-                       C=torch.from_numpy(d["C"]).to(DEV), **opts)
+        os.environ["SROT_LMO_SCREEN"] = "0"
+        try:
+            sol = S.Solver(torch.from_numpy(d["a"]).to(DEV), torch.from_numpy(d["b"]).to(DEV),
+                           C=torch.from_numpy(d["C"]).to(DEV), **opts)
+        finally:
+            del os.environ["SROT_LMO_SCREEN"]
         s1, (g, f, D), np1 = sol.solve()
         T1, r1 = sol.plan()
         T2, r2 = bs.plan(p)
