@@ -24,7 +24,8 @@
 // one per lane.  Every other column j satisfies, at the time the screen read
 // r, c_ij + w r_j >= tau - e with e the FP32 error bound of the screen; until
 // the step is taken r_j can only have dropped by the decreases of the steps
-// in between, each at most gamma a_i of that step.  The stepper evaluates
+// in between: a step scales the row's entries off its vertex by 1 - gamma,
+// so no r_j drops by more than gamma times the largest of them.  The stepper evaluates
 // the candidates in FP64 at the current r and accepts their minimum only if
 // it lies strictly below tau - e - w (sum of those decreases): then every
 // other column is strictly larger, and the smallest candidate (lowest column
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 // line-search partials over the support of row i
                 uint32_t wg[4] = {wdv.x, wdv.y, wdv.z, wdv.w};
                 double pp = 0.0, q2 = 0.0, tj = 0.0, ts = 0.0;
+                double toff_max = 0.0;  // largest entry off the vertex: it drops by gamma times it
                 bool star_l = false;
                 if (!stale) {
 #pragma unroll
@@ -256,6 +258,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                         q2 += (has && !atj) ? t * t : 0.0;
                         tj += atj ? t : 0.0;
                         ts += t;
+                        toff_max = fmax(toff_max, atj ? 0.0 : t);
                         star_l |= atj;
                     }
                 } else {
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                             q2 += atj ? 0.0 : t * t;
                             tj += atj ? t : 0.0;
                             ts += t;
+                            toff_max = fmax(toff_max, atj ? 0.0 : t);
                             star_l |= atj;
                         }
                     }
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 }
                 // each partial summed over the lanes holding nonzeros, in lane order
                 // (rows have few nonzeros: cheaper than a full wave reduction)
-                double sp = 0.0, sq2 = 0.0, stj = 0.0;
+                double sp = 0.0, sq2 = 0.0, stj = 0.0, smax = 0.0;
                 {
                     unsigned long long act = __ballot(ts != 0.0 || pp != 0.0 || q2 != 0.0 || tj != 0.0);
                     while (act) {
@@ -296,6 +300,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                         sp += readlane_f64(pp, l);
                         sq2 += readlane_f64(q2, l);
                         stj += readlane_f64(tj, l);
+                        smax = fmax(smax, readlane_f64(toff_max, l));
                     }
                 }
                 const bool star_in = __any(star_l);
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 hist[0] = i;
 #pragma unroll
                 for (int k = SC_DECN - 1; k > 0; --k) dec[k] = dec[k - 1];
-                dec[0] = gadd;
+                dec[0] = gamma * smax;
                 // every store of earlier steps is complete before the barrier
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(NST));
             }
