@@ -88,7 +88,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
     static_assert(CPT == 8 || CPT == 16, "4 owner threads x CPT columns per lane");
     constexpr int NC = 256 * CPT;   // columns of the ownership (n <= NC)
     constexpr int G = CPT / 4;      // 16-byte groups per owner thread
-    constexpr int NST = SC_KS + 1 + 4 + (TRACE ? 2 : 0);  // stores issued by every step
+    constexpr int NST = SC_KS + 1 + 1 + (TRACE ? 2 : 0);  // stores issued by every step
     __shared__ __align__(16) double r64[NC];
     __shared__ __align__(16) float r32[NC];
     __shared__ int s_i[SC_SLOTS];
@@ -188,6 +188,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 for (int k = 0; k < SC_DECN; ++k) dsum += dec[k];
                 const double bound = (double)tau - err - w * dsum;
                 int jstar;
+                bool fell = false;
                 if (vstar < bound) {
                     unsigned long long hit = __ballot(vc == vstar);
                     int jw = 0x7fffffff;
@@ -198,6 +199,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     }
                     jstar = jw;
                 } else {
+                    fell = true;
                     // full row: the columns of owner threads lane + 64 h
                     ++n_fall;
                     const float4 *__restrict__ crow4 = reinterpret_cast<const float4 *>(C + (size_t)i * (size_t)n);
@@ -240,7 +242,8 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     jstar = bj;
                     drain_memory();
                 }
-                const double rstar = r64[jstar];
+                // the owner lane of j* held it as its candidate on the fast path
+                const double rstar = fell ? r64[jstar] : rc;
 
                 // line-search partials over the support of row i
                 uint32_t wg[4] = {wdv.x, wdv.y, wdv.z, wdv.w};
@@ -308,9 +311,9 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 const double gadd = gamma * ai;
 
                 // t_i <- (1 - gamma) t_i + gamma a_i e_j*, r <- r + (t_i new - t_i old)
-                uint32_t nw[4] = {wg[0], wg[1], wg[2], wg[3]};
                 double tnv[SC_KS];
                 unsigned toff[SC_KS];
+                bool zero_l = false;  // a nonzero of this lane became 0 (gamma = 1)
 #pragma unroll
                 for (int k = 0; k < SC_KS; ++k) {
                     const bool has = sq[k] >= 0;
@@ -318,18 +321,16 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     const double tn = blend(st[k], gamma, atj ? gadd : 0.0);
                     const bool put = has && tn != st[k];
                     const int col = has ? sq[k] : 0;
+                    const double rn = sr[k] + (tn - st[k]);
                     if (put) {
-                        const double rn = sr[k] + (tn - st[k]);
                         r64[col] = rn;
                         r32[col] = (float)rn;
                     }
-                    const int tq = (col >> 2) & 255, u = ((col >> 10) << 2) | (col & 3);
-#pragma unroll
-                    for (int h = 0; h < 4; ++h)
-                        nw[h] = (has && tn == 0.0 && (tq >> 6) == h) ? (nw[h] & ~(1u << u)) : nw[h];
+                    zero_l |= has && tn == 0.0;
                     tnv[k] = tn;
                     toff[k] = put ? (unsigned)col * 8u : kOOB;
                 }
+                uint32_t nw[4] = {wg[0], wg[1], wg[2], wg[3]};
                 if (stale) {
                     double *__restrict__ trow = T + (size_t)i * (size_t)n;
 #pragma unroll
@@ -354,30 +355,49 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 }
                 const double tsn = blend(0.0, gamma, gadd);
                 const int oq = (jstar >> 2) & 255;
+                const int hs = oq >> 6, us = ((jstar >> 10) << 2) | (jstar & 3);
                 const bool put_s = ((oq & 63) == lane) && !star_in && tsn != 0.0;
+                const double rns = rstar + tsn;
                 if (put_s) {
-                    const double rn = rstar + tsn;
-                    r64[jstar] = rn;
-                    r32[jstar] = (float)rn;
+                    r64[jstar] = rns;
+                    r32[jstar] = (float)rns;
                 }
-                {
-                    const int u = ((jstar >> 10) << 2) | (jstar & 3);
-#pragma unroll
-                    for (int h = 0; h < 4; ++h) nw[h] = (put_s && (oq >> 6) == h) ? (nw[h] | (1u << u)) : nw[h];
-                }
-                // the step's stores: a fixed sequence (absent ones out of range)
+                // the step's stores: a fixed sequence (absent ones out of range):
+                // the plan entries and the new vertex's mask word
                 const __amdgpu_buffer_rsrc_t rt = buf_rsrc(T + (size_t)i * (size_t)n, row_bytes);
 #pragma unroll
                 for (int k = 0; k < SC_KS; ++k) buf_store_f64(tnv[k], rt, toff[k]);
                 buf_store_f64(tsn, rt, put_s ? (unsigned)jstar * 8u : kOOB);
                 const __amdgpu_buffer_rsrc_t rm = buf_rsrc(M + (size_t)i * 256, 256u * 4u);
-#pragma unroll
-                for (int h = 0; h < 4; ++h) buf_store_u32(nw[h], rm, nw[h] != wg[h] ? (unsigned)(lane + 64 * h) * 4u : kOOB);
+                {
+                    const uint32_t ws = (hs == 0 ? nw[0] : hs == 1 ? nw[1] : hs == 2 ? nw[2] : nw[3]) | (1u << us);
+                    buf_store_u32(ws, rm, (put_s && !stale) ? (unsigned)oq * 4u : kOOB);
+                }
                 if constexpr (TRACE) {
                     const __amdgpu_buffer_rsrc_t rs_tj = buf_rsrc(trace_j, trace_j ? (unsigned)nsteps * 4u : 0u);
                     const __amdgpu_buffer_rsrc_t rs_tg = buf_rsrc(trace_gamma, trace_gamma ? (unsigned)nsteps * 8u : 0u);
                     buf_store_u32((unsigned)jstar, rs_tj, lane == 0 ? (unsigned)s * 4u : kOOB);
                     buf_store_f64(gamma, rs_tg, lane == 0 ? (unsigned)s * 8u : kOOB);
+                }
+                // rare: nonzeros that became 0 leave the support (and every word
+                // of a row re-read from the plan is rewritten as computed)
+                if (stale || __any(zero_l)) {
+                    if (!stale) {
+#pragma unroll
+                        for (int k = 0; k < SC_KS; ++k) {
+                            const int col = sq[k] >= 0 ? sq[k] : 0;
+                            const int hk = ((col >> 2) & 255) >> 6, uk = ((col >> 10) << 2) | (col & 3);
+                            const bool clr = sq[k] >= 0 && tnv[k] == 0.0;
+#pragma unroll
+                            for (int h = 0; h < 4; ++h) nw[h] = (clr && hk == h) ? (nw[h] & ~(1u << uk)) : nw[h];
+                        }
+                    }
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) nw[h] = (put_s && hs == h) ? (nw[h] | (1u << us)) : nw[h];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        buf_store_u32(nw[h], rm, nw[h] != wg[h] ? (unsigned)(lane + 64 * h) * 4u : kOOB);
+                    drain_memory();
                 }
 #pragma unroll
                 for (int k = SC_HIST - 1; k > 0; --k) hist[k] = hist[k - 1];
@@ -486,8 +506,11 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
 #pragma unroll
                     for (int h = 0; h < 4; ++h) bits |= (uint64_t)(wd[h] & low) << (h * CPT);
                     const bool over = __popcll(bits) > SC_KS;
-                    const __amdgpu_buffer_rsrc_t rt = buf_rsrc(T + (size_t)ri * (size_t)n, row_bytes);
-                    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(C + (size_t)ri * (size_t)n, (unsigned)n * 4u);
+                    // the row index is wave-uniform: scalar buffer descriptors (a
+                    // descriptor in vector registers costs a loop per load)
+                    const int rw = __builtin_amdgcn_readfirstlane(ri);
+                    const __amdgpu_buffer_rsrc_t rt = buf_rsrc(T + (size_t)rw * (size_t)n, row_bytes);
+                    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(C + (size_t)rw * (size_t)n, (unsigned)n * 4u);
 #pragma unroll
                     for (int k = 0; k < SC_KS; ++k) {
                         const int b = bits ? __ffsll((long long)bits) - 1 : -1;
