@@ -25,8 +25,8 @@
 // r, c_ij + w r_j >= tau - e with e the FP32 error bound of the screen; until
 // the step is taken r_j can only have dropped by the decreases of the steps
 // in between: a step scales the row's entries off its vertex by 1 - gamma,
-// so no r_j drops by more than gamma times the largest of them.  The stepper evaluates
-// the candidates in FP64 at the current r and accepts their minimum only if
+// so no r_j drops by more than gamma times the largest of them.  The stepper
+// evaluates the candidates in FP64 at the current r and accepts their minimum only if
 // it lies strictly below tau - e - w (sum of those decreases): then every
 // other column is strictly larger, and the smallest candidate (lowest column
 // on ties) is the exact lowest-index argmin of the full row.  Otherwise the
