@@ -1115,26 +1115,26 @@ __global__ void sample_uniform_kernel(uint64_t seed, int64_t k0, int64_t count, 
 __global__ __launch_bounds__(256) void sample_permute_kernel(uint64_t seed, int64_t p0, int32_t m,
                                                              int32_t *__restrict__ out)
 {
+    // grid: (ceil(m / 256) key tiles, passes); each thread ranks one key of
+    // its pass against all m keys of that pass (stable: ties by position)
     __shared__ uint64_t tile[256];
-    const int64_t p = p0 + blockIdx.x;
-    int32_t *o = out + (int64_t)blockIdx.x * m;
-    for (int32_t tb = 0; tb < m; tb += 256) {
-        const int32_t t = tb + threadIdx.x;
-        const uint64_t kt = (t < m) ? philox_output(seed, (uint64_t)(p * m + t)) : 0ull;
-        int32_t rank = 0;
-        for (int32_t ub = 0; ub < m; ub += 256) {
-            const int32_t u = ub + threadIdx.x;
-            tile[threadIdx.x] = (u < m) ? philox_output(seed, (uint64_t)(p * m + u)) : 0ull;
-            __syncthreads();
-            const int32_t lim = min(256, m - ub);
-            for (int32_t q = 0; q < lim; ++q) {
-                const uint64_t ku = tile[q];
-                rank += (ku < kt) || (ku == kt && ub + q < t);
-            }
-            __syncthreads();
+    const int64_t p = p0 + blockIdx.y;
+    int32_t *o = out + (int64_t)blockIdx.y * m;
+    const int32_t t = (int32_t)blockIdx.x * 256 + (int32_t)threadIdx.x;
+    const uint64_t kt = (t < m) ? philox_output(seed, (uint64_t)(p * m + t)) : 0ull;
+    int32_t rank = 0;
+    for (int32_t ub = 0; ub < m; ub += 256) {
+        const int32_t u = ub + threadIdx.x;
+        tile[threadIdx.x] = (u < m) ? philox_output(seed, (uint64_t)(p * m + u)) : 0ull;
+        __syncthreads();
+        const int32_t lim = min(256, m - ub);
+        for (int32_t q = 0; q < lim; ++q) {
+            const uint64_t ku = tile[q];
+            rank += (ku < kt) || (ku == kt && ub + q < t);
         }
-        if (t < m) o[rank] = t;
+        __syncthreads();
     }
+    if (t < m) o[rank] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -1266,9 +1266,15 @@ hipError_t launch_sample_uniform(uint64_t seed, int64_t k0, int64_t count, int32
 hipError_t launch_sample_permute(uint64_t seed, int64_t p0, int64_t npasses, int32_t m,
                                  int32_t *out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(sample_permute_kernel, dim3((unsigned)npasses), dim3(256), 0, stream, seed,
-                       p0, m, out);
-    return hipGetLastError();
+    // passes along the grid's second dimension, at most 65535 per launch
+    for (int64_t c = 0; c < npasses; c += 65535) {
+        const int64_t np = std::min<int64_t>(65535, npasses - c);
+        hipLaunchKernelGGL(sample_permute_kernel, dim3((unsigned)((m + 255) / 256), (unsigned)np), dim3(256), 0,
+                           stream, seed, p0 + c, m, out + c * (int64_t)m);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int COST>

@@ -609,8 +609,11 @@ bool screened_chain_enabled()
 hipError_t launch_cost_bounds(const ProblemView &P, const DeviceState &S, double *out2, hipStream_t stream)
 {
     const size_t count = (size_t)P.m * (size_t)P.n;
+    // one partial per workgroup in the gap partial buffer (at least
+    // 8 * gap_blocks doubles)
     int blocks = (int)((count + 256 * 64 - 1) / (256 * 64));
     if (blocks > 1024) blocks = 1024;
+    if (blocks > 8 * S.gap_blocks) blocks = 8 * S.gap_blocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(cost_absmax_kernel, dim3(blocks), dim3(256), 0, stream, (const float *)P.C, count,
                        S.partials);
