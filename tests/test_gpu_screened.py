@@ -203,3 +203,25 @@ def test_solve_to_gap_with_the_screened_chain():
     _, hist = O.solve(P, lambda p: I.philox_uniform_indices(4, p * m, m, m), eps=eps, max_passes=1500)
     assert abs(f - hist[-1]["f"]) <= g + hist[-1]["g"] + 1e-12
     sol.close()
+
+
+def test_permutation_sampling_on_the_screened_chain():
+    """Per-pass permutation sampling (numpy's Philox, keys sorted stably) with
+    m = 700 rows, i.e. three 256-key tiles of the sampler and a ragged one,
+    over three passes drawn in uneven calls, on the screened chain."""
+    S = _S()
+    m, n, w = 700, 1028, 1.0
+    d = I.problem_mixture(43, m, n)
+    idx = I.philox_permutation_indices(17, 0, 3, m)
+    P = O.Problem(d["a"], d["b"], w, C=d["C"].astype(np.float64))
+    st = O.State(P)
+    otr = O.bcfw_steps(P, st, idx)
+    sol = _solver(d, w, seed=17, sampling=S.SROT_PERMUTE)
+    gjs, ggs = [], []
+    for c in (1, 699, 350, 1050):
+        gj, gg = sol.step(c, trace=True)
+        gjs.append(gj)
+        ggs.append(gg)
+    _compare(otr, torch.cat(gjs), torch.cat(ggs))
+    _check_plan(sol, st, d)
+    sol.close()
