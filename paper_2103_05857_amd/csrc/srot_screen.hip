@@ -53,7 +53,7 @@ namespace srot {
 constexpr int SC_NW = 8;
 constexpr int SC_NT = SC_NW * 64;
 constexpr int SC_SLOTS = 8;    // rows in preparation (steps s .. s + 3 in use)
-constexpr int SC_KS = 2;       // nonzeros per screener lane in the prepared support
+constexpr int SC_KS = 2;       // nonzeros per screener lane in the prepared support (two slot fields)
 constexpr int SC_HIST = 8;     // a row updated within this many steps is re-read by the stepper
 constexpr int SC_DECN = 3;     // steps whose residual decreases a screen may have missed
 constexpr int LAG_A = 7, LAG_B1 = 3, LAG_B2 = 2, LAG_C = 1;
@@ -91,16 +91,15 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
     constexpr int NST = SC_KS + 1 + 1 + (TRACE ? 2 : 0);  // stores issued by every step
     __shared__ __align__(16) double r64[NC];
     __shared__ __align__(16) float r32[NC];
-    __shared__ int s_i[SC_SLOTS];
-    __shared__ double s_a[SC_SLOTS];
-    __shared__ float s_tau[SC_SLOTS];
-    __shared__ int s_ovf[SC_SLOTS];
-    __shared__ int s_cj[SC_SLOTS][64];
-    __shared__ float s_cc[SC_SLOTS][64];
-    __shared__ int s_aq[SC_SLOTS][SC_KS][64];
-    __shared__ double s_at[SC_SLOTS][SC_KS][64];
-    __shared__ float s_ac[SC_SLOTS][SC_KS][64];
-    __shared__ uint4 s_wd[SC_SLOTS][64];
+    // a prepared row: header (row, a_i, tau, overflow flag) and, per lane,
+    // 16-byte groups that the stepper reads with one instruction each:
+    // {candidate column, its cost, two nonzero columns}, {their plan
+    // entries}, {their costs}, {the four support-mask words}
+    __shared__ __align__(16) int4 s_hdr[SC_SLOTS][2];       // {i, ovf, tau bits, -}, {a_i bits}
+    __shared__ __align__(16) int4 s_g0[SC_SLOTS][64];
+    __shared__ __align__(16) double2 s_g1[SC_SLOTS][64];
+    __shared__ __align__(16) float2 s_g2[SC_SLOTS][64];
+    __shared__ __align__(16) uint4 s_wd[SC_SLOTS][64];
     __shared__ double s_rmax[SC_NW];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -155,20 +154,25 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 // =============================== stepper: block step s = p
                 const int64_t s = p;
                 const int q = (int)(s & (SC_SLOTS - 1));
-                const int i = __builtin_amdgcn_readfirstlane(s_i[q]);
-                const double ai = s_a[q];
-                const float tau = s_tau[q];
-                const int ovf = s_ovf[q];
-                const int cj = s_cj[q][lane];
-                const float cc = s_cc[q][lane];
+                const int4 h0 = s_hdr[q][0];
+                const int4 h1 = s_hdr[q][1];
+                const int4 g0 = s_g0[q][lane];
+                const double2 g1 = s_g1[q][lane];
+                const float2 g2 = s_g2[q][lane];
+                const int i = __builtin_amdgcn_readfirstlane(h0.x);
+                const int ovf = h0.y;
+                const float tau = __int_as_float(h0.z);
+                const double ai = __hiloint2double(h1.y, h1.x);
+                const int cj = g0.x;
+                const float cc = __int_as_float(g0.y);
                 int sq[SC_KS];
                 double st[SC_KS];
                 float sc[SC_KS];
 #pragma unroll
                 for (int k = 0; k < SC_KS; ++k) {
-                    sq[k] = s_aq[q][k][lane];
-                    st[k] = s_at[q][k][lane];
-                    sc[k] = s_ac[q][k][lane];
+                    sq[k] = k == 0 ? g0.z : g0.w;
+                    st[k] = k == 0 ? g1.x : g1.y;
+                    sc[k] = k == 0 ? g2.x : g2.y;
                 }
                 const uint4 wdv = s_wd[q][lane];
                 bool stale = ovf != 0;
@@ -467,12 +471,9 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 const int64_t s = p + LAG_C;
                 if (s >= 0 && s < nsteps) {
                     const int q = (int)(s & (SC_SLOTS - 1));
-#pragma unroll
-                    for (int k = 0; k < SC_KS; ++k) {
-                        s_aq[q][k][lane] = aq[k];
-                        s_at[q][k][lane] = atv[k];
-                        s_ac[q][k][lane] = acv[k];
-                    }
+                    *reinterpret_cast<int2 *>(&s_g0[q][lane].z) = make_int2(aq[0], aq[1]);
+                    s_g1[q][lane] = make_double2(atv[0], atv[1]);
+                    s_g2[q][lane] = make_float2(acv[0], acv[1]);
                 }
                 // A: loads for the row of step p + LAG_A
                 const int64_t s2 = p + LAG_A;
@@ -523,9 +524,10 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     }
                     const bool any_over = __any(over);
                     if (lane == 0) {
-                        s_i[q] = ri;
-                        s_a[q] = ra;
-                        s_ovf[q] = any_over ? 1 : 0;
+                        s_hdr[q][0].x = ri;
+                        s_hdr[q][0].y = any_over ? 1 : 0;
+                        s_hdr[q][1].x = __double2loint(ra);
+                        s_hdr[q][1].y = __double2hiint(ra);
                     }
                     s_wd[q][lane] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
                 }
@@ -538,9 +540,8 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     screen_cols(3);
                     const float tau = wave_min_f32(m2);
                     const int jc = j1 >= 0 ? owned_col<256, 4>(j1 % CPT, lane + 64 * (j1 / CPT)) : -1;
-                    s_cj[q][lane] = (m1 < tau) ? jc : -1;
-                    s_cc[q][lane] = c1;
-                    if (lane == 0) s_tau[q] = tau;
+                    *reinterpret_cast<int2 *>(&s_g0[q][lane].x) = make_int2((m1 < tau) ? jc : -1, __float_as_int(c1));
+                    if (lane == 0) s_hdr[q][0].z = __float_as_int(tau);
                 }
             }
             pm = (pm == 5) ? 0 : pm + 1;
