@@ -225,3 +225,21 @@ def test_permutation_sampling_on_the_screened_chain():
     _compare(otr, torch.cat(gjs), torch.cat(ggs))
     _check_plan(sol, st, d)
     sol.close()
+
+
+def test_zero_penalty_closed_form_on_the_screened_chain():
+    """w = 0: every block step moves its row to a_i at the row's smallest
+    cost, lowest column on ties (the closed form of the zero-penalty limit),
+    whatever the residual; one pass in a random order reaches it exactly."""
+    m, n = 200, 2048
+    d = I.problem_mixture(44, m, n)
+    sol = _solver(d, 0.0)
+    perm = np.random.default_rng(1).permutation(m).astype(np.int32)
+    sol.step(m, idx=torch.from_numpy(perm).to(DEV))
+    T, _ = sol.plan()
+    Texp = np.zeros((m, n))
+    Texp[np.arange(m), np.argmin(d["C"], axis=1)] = d["a"]
+    np.testing.assert_array_equal(T.cpu().numpy(), Texp)
+    g, f, D = sol.gap()
+    assert g == 0.0
+    sol.close()
