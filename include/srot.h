@@ -175,6 +175,9 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
  *            (rows updated within the last 8 steps, or rows with more
  *            nonzeros per screener lane than prepared);
  *   out4[2], out4[3]  0 (reserved).
+ * The chains for rows of up to 4096 columns with a register-resident
+ * residual write these counts at every launch; the wide-row chains (more
+ * than 4096 columns) leave them as they were (0 after srot_init).
  * Neither changes any result: every path takes the same exact step.
  * Setting SROT_LMO_SCREEN=0 in the environment before srot_init selects the
  * unscreened chain for that handle. */
