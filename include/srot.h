@@ -168,7 +168,7 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
  * pass of srot_solve), written to out4 (host, 4 int64; synchronises):
  *   out4[0]  steps whose LMO (eq. SemiRelaxedSubproblemImplement) scanned the
  *            full row outside the chain's fast path: with the screened LMO
- *            (stored FP32 cost, 1025-4096 columns), steps where the
+ *            (stored FP32 cost, 513-4096 columns), steps where the
  *            candidates could not be certified; otherwise steps taken by the
  *            one-at-a-time tail path;
  *   out4[1]  screened LMO only: steps whose support was re-read from the plan

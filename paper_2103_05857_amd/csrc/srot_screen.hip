@@ -1,5 +1,5 @@
 // Block-step chain with a screened LMO (Alg. 1, stored FP32 cost, rows of
-// 1025..4096 columns in the 256 x {8,16} x 4 column ownership).
+// 513..4096 columns in the 256 x {4,8,16} x 4 column ownership).
 //
 // The block steps stay strictly sequential and exact; what changes is who
 // does the per-column work.  One workgroup of eight waves:
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                                                                double *__restrict__ trace_gamma,
                                                                int64_t *__restrict__ slow_steps, double err_c)
 {
-    static_assert(CPT == 8 || CPT == 16, "4 owner threads x CPT columns per lane");
+    static_assert(CPT == 4 || CPT == 8 || CPT == 16, "4 owner threads x CPT columns per lane");
     constexpr int NC = 256 * CPT;   // columns of the ownership (n <= NC)
     constexpr int G = CPT / 4;      // 16-byte groups per owner thread
     constexpr int NST = SC_KS + 1 + 1 + (TRACE ? 2 : 0);  // stores issued by every step
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(256) void cost_bound_finish_kernel(ProblemView P, c
 bool screened_chain_supported(const ProblemView &P, const DeviceState &S)
 {
     const Ownership &o = S.own;
-    return P.cost == SROT_COST_F32 && o.reg && o.nt == 256 && o.vec == 4 && (o.cpt == 8 || o.cpt == 16);
+    return P.cost == SROT_COST_F32 && o.reg && o.nt == 256 && o.vec == 4 && (o.cpt == 4 || o.cpt == 8 || o.cpt == 16);
 }
 
 bool screened_chain_enabled()
@@ -639,6 +639,7 @@ hipError_t launch_chain_screened(const ProblemView &P, const DeviceState &S, con
                                S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.slow_steps, S.screen_err); \
         return hipGetLastError();                                                                    \
     }
+    SROT_SCREENED(4)
     SROT_SCREENED(8)
     SROT_SCREENED(16)
 #undef SROT_SCREENED

@@ -16,6 +16,8 @@ and is widened exactly):
     1e-6 * max(g, 1e-9) + 1e-15 (the stated 1e-6 relative tolerance, with an absolute
     floor for FP64 rounding of a tiny difference).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -287,7 +289,9 @@ def test_rows_with_more_atoms_per_thread_than_prefetched():
     """Rows whose support holds three or four columns of one thread (adjacent
     columns of one 16-byte group) exceed the support entries the prefetching
     chain reads ahead; the chain then stops and the tail kernel finishes the
-    launch.  The first such row is visited after 50 ordinary steps."""
+    launch.  The first such row is visited after 50 ordinary steps.  (The
+    handle is created with SROT_LMO_SCREEN=0: at 1024 columns the default is
+    the screened chain, whose own test covers such rows.)"""
     _need_gpu()
     m, n, w = 64, 1024, 1.0
     d = I.problem_mixture(19, m, n)
@@ -306,7 +310,11 @@ def test_rows_with_more_atoms_per_thread_than_prefetched():
     P = _oracle_problem(d, "stored", w)
     st = O.State(P, T)
     otr = O.bcfw_steps(P, st, idx, rule=O.ELS)
-    sol = _gpu_problem(d, "stored", w)
+    os.environ["SROT_LMO_SCREEN"] = "0"
+    try:
+        sol = _gpu_problem(d, "stored", w)
+    finally:
+        del os.environ["SROT_LMO_SCREEN"]
     sol.set_state(torch.from_numpy(T).to(DEV), 0)
     gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
     _compare_traces(otr, gj, gg)

@@ -1,4 +1,4 @@
-"""The screened-LMO block-step chain (stored FP32 cost, rows of 1025-4096
+"""The screened-LMO block-step chain (stored FP32 cost, rows of 513-4096
 columns) against the FP64 oracle, step by step, and on each of its paths:
 candidates certified by the screen's bound, the full-row scan when they
 cannot be, and the support re-read from the plan for recently updated rows
@@ -67,6 +67,8 @@ def _check_plan(sol, st, d):
     (300, 3000, 0.1, "els", 3),     # ragged row (n not a multiple of 1024)
     (6, 1028, 1.0, "els", 80),      # most rows repeat within 8 steps: support re-read
     (64, 4092, 1.0, "dec", 5),      # decay step
+    (80, 1024, 1.0, "els", 6),      # 4 columns per owner thread
+    (50, 516, 10.0, "els", 8),      # the narrowest screened rows, mostly past the end
 ])
 def test_screened_traces_match_oracle(m, n, w, rule, passes):
     S = _S()
