@@ -69,6 +69,7 @@ def _check_plan(sol, st, d):
     (64, 4092, 1.0, "dec", 5),      # decay step
     (80, 1024, 1.0, "els", 6),      # 4 columns per owner thread
     (50, 516, 10.0, "els", 8),      # the narrowest screened rows, mostly past the end
+    (30, 2048, 100.0, "els", 12),   # large steps in r: many full-row scans
 ])
 def test_screened_traces_match_oracle(m, n, w, rule, passes):
     S = _S()
@@ -85,6 +86,8 @@ def test_screened_traces_match_oracle(m, n, w, rule, passes):
     _check_plan(sol, st, d)
     if m <= 6:
         assert stats[1] > 0.5 * len(idx)        # most rows were updated within 8 steps
+    if w >= 100.0:
+        assert stats[0] > 0                      # the certificate failed on some steps
     sol.close()
 
 
