@@ -174,14 +174,21 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
  *   out4[1]  screened LMO only: steps whose support was re-read from the plan
  *            (rows updated within the last 8 steps, or rows with more
  *            nonzeros per screener lane than prepared);
- *   out4[2], out4[3]  0 (reserved).
+ *   out4[2]  which chain kernel ran the last launch, written by the kernel
+ *            itself: SROT_CHAIN_PREFETCH, SROT_CHAIN_SCREENED,
+ *            SROT_CHAIN_GLOBAL or SROT_CHAIN_WIDE (0 before any launch);
+ *   out4[3]  0 (reserved).
  * The chains for rows of up to 4096 columns with a register-resident
- * residual write these counts at every launch; the wide-row chains (more
- * than 4096 columns) leave them as they were (0 after srot_init).
+ * residual write out4[0] and out4[1] at every launch; the wide-row chains
+ * (more than 4096 columns) leave them as they were (0 after srot_init).
  * Neither changes any result: every path takes the same exact step.
  * Setting SROT_LMO_SCREEN=0 in the environment before srot_init selects the
  * unscreened chain for that handle. */
 int srot_chain_stats(srot_handle *h, int64_t *out4);
+#define SROT_CHAIN_PREFETCH  1   /* one workgroup, rows prefetched, r in LDS   */
+#define SROT_CHAIN_SCREENED  2   /* stepper wave over FP32-screened candidates */
+#define SROT_CHAIN_GLOBAL    3   /* stored cost wider than 4096 columns        */
+#define SROT_CHAIN_WIDE      4   /* fused cost wider than 4096 columns         */
 
 /* Gradients of the optimal value V = min f (the problem above) with respect
  * to the inputs, evaluated at the handle's current plan T and scaled by

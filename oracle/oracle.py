@@ -58,7 +58,7 @@ def _load():
                                   _i32p, _i32p, _dp, _dp, _i32p, _i32p, ctypes.c_double]
     lib.or_bcfw_steps.restype = ctypes.c_int
     lib.or_active_steps.argtypes = [P, _dp, _dp, _i64p, ctypes.c_int, ctypes.c_int64, _i32p, _i32p, _i32p,
-                                    _dp, _dp, _i32p, _dp, _i32p, ctypes.c_double]
+                                    _dp, _dp, _i32p, _dp, _i32p, _dp, ctypes.c_double]
     lib.or_active_steps.restype = ctypes.c_int
     lib.or_fw_iteration.argtypes = [P, _dp, ctypes.c_int64, ctypes.c_int, _dp]
     lib.or_fw_iteration.restype = ctypes.c_double
@@ -220,21 +220,24 @@ def active_steps(P, state, idx, variant, trace=True, near_tol=1e-12):
     """Runs len(idx) block steps with away steps (variant AWAY, Alg. A.2) or
     pairwise steps (PAIRWISE, Alg. A.3) in place on state.
 
-    Returns dict(j, away, gamma, margin, near, amargin, anear) when trace is set."""
+    Returns dict(j, away, gamma, margin, near, amargin, anear, dslope) when
+    trace is set; dslope is the FW slope minus the away slope of the BCAFW
+    direction choice (NaN where no choice is made)."""
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     ns = idx.shape[0]
     out = None
     if trace:
         out = dict(j=np.empty(ns, np.int32), away=np.empty(ns, np.int32), gamma=np.empty(ns),
                    margin=np.empty(ns), near=np.empty((ns, 4), np.int32), amargin=np.empty(ns),
-                   anear=np.empty((ns, 4), np.int32))
+                   anear=np.empty((ns, 4), np.int32), dslope=np.empty(ns))
     g = (lambda key, ct: _ptr(out[key], ct)) if trace else (lambda key, ct: None)
     k = ctypes.c_int64(state.k)
     rc = _load().or_active_steps(P.ref, _ptr(state.T, ctypes.c_double), _ptr(state.r, ctypes.c_double),
                                  ctypes.byref(k), int(variant), ns, _ptr(idx, ctypes.c_int32),
                                  g("j", ctypes.c_int32), g("away", ctypes.c_int32), g("gamma", ctypes.c_double),
                                  g("margin", ctypes.c_double), g("near", ctypes.c_int32),
-                                 g("amargin", ctypes.c_double), g("anear", ctypes.c_int32), float(near_tol))
+                                 g("amargin", ctypes.c_double), g("anear", ctypes.c_int32),
+                                 g("dslope", ctypes.c_double), float(near_tol))
     if rc != 0:
         raise ValueError("block index out of range")
     state.k = k.value

@@ -290,11 +290,13 @@ int or_bcfw_steps(const or_problem *P, double *T, double *r, int64_t *k,
  * FW direction was taken); tr_gamma; tr_margin / tr_near as in
  * or_bcfw_steps; tr_amargin = largest minus second-largest gradient value on
  * the active set (INFINITY with one atom) and tr_anear = the first four
- * active columns within near_tol of the largest (-1 padded). */
+ * active columns within near_tol of the largest (-1 padded); tr_dslope =
+ * <-g, d_FW> - <-g, d_A>, the margin of the BCAFW direction choice (NAN when
+ * no choice is made: pairwise steps, one atom, or ja = js). */
 int or_active_steps(const or_problem *P, double *T, double *r, int64_t *k, int pairwise,
                     int64_t nsteps, const int32_t *idx, int32_t *tr_j, int32_t *tr_away,
                     double *tr_gamma, double *tr_margin, int32_t *tr_near,
-                    double *tr_amargin, int32_t *tr_anear, double near_tol)
+                    double *tr_amargin, int32_t *tr_anear, double *tr_dslope, double near_tol)
 {
     const int64_t m = P->m, n = P->n;
     double *grad = (double *)malloc(sizeof(double) * (size_t)n);
@@ -315,7 +317,7 @@ int or_active_steps(const or_problem *P, double *T, double *r, int64_t *k, int p
                 ++natoms;
                 if (ja < 0 || grad[j] > grad[ja]) ja = j;
             }
-        double gamma = 0.0;
+        double gamma = 0.0, dslope = NAN;
         int fw_dir = 0, drop = 0;
         for (int64_t j = 0; j < n; ++j) old[j] = t_i[j];
         if (ja >= 0) {
@@ -333,6 +335,7 @@ int or_active_steps(const or_problem *P, double *T, double *r, int64_t *k, int p
                 /* with one atom, or the away vertex at the FW vertex, the away
                  * direction is zero in exact arithmetic: take the FW one */
                 fw_dir = natoms == 1 || ja == js || slope_fw >= slope_aw;
+                if (natoms > 1 && ja != js) dslope = slope_fw - slope_aw;
                 if (fw_dir) {
                     for (int64_t j = 0; j < n; ++j) d[j] = (j == js ? ai : 0.0) - t_i[j];
                     gmax = 1.0;
@@ -367,6 +370,7 @@ int or_active_steps(const or_problem *P, double *T, double *r, int64_t *k, int p
         if (tr_j) tr_j[st] = (int32_t)js;
         if (tr_away) tr_away[st] = (int32_t)(fw_dir ? -1 - ja : ja);
         if (tr_gamma) tr_gamma[st] = gamma;
+        if (tr_dslope) tr_dslope[st] = dslope;
         if (tr_margin) tr_margin[st] = margin;
         if (tr_near) {
             int cnt = 0;

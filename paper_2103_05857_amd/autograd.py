@@ -11,6 +11,8 @@ cost), and to a and b.  They are the envelope-theorem derivatives, exact
 at an optimal plan; at the plan where the solver stopped (duality gap <= eps)
 their accuracy follows from that gap.
 """
+import warnings
+
 import torch
 
 from . import srot as S
@@ -26,6 +28,12 @@ class SemiRelaxedOT(torch.autograd.Function):
                        Y=Y.detach().contiguous() if fused else None,
                        w=float(w), eps=float(eps), max_passes=int(max_passes), seed=int(seed))
         status, (g, f, D), passes = sol.solve()
+        if status != S.SROT_OK:
+            # an unconverged plan: V is an upper bound within g of the
+            # optimum, and the envelope gradients are only approximate
+            warnings.warn(f"semi_relaxed_ot: no convergence to gap {eps:g} in {passes} passes "
+                          f"(gap {g:.3e}); the value and its gradients are those of the last plan",
+                          RuntimeWarning, stacklevel=3)
         ctx.sol = sol
         ctx.fused = fused
         ctx.info = dict(status=status, gap=g, f=f, dual=D, passes=passes)

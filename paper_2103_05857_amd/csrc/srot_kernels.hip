@@ -51,7 +51,10 @@ __global__ __launch_bounds__(NT) void chain_kernel(ProblemView P, double *__rest
 {
     const int64_t slow = chain_run<NT, CPT, VEC, COST, TRACE>(P, T, rg, M, idx, k0, nsteps, rule,
                                                              trace_j, trace_gamma);
-    if (threadIdx.x == 0) *slow_steps = slow;
+    if (threadIdx.x == 0) {
+        slow_steps[0] = slow;
+        slow_steps[2] = SROT_CHAIN_PREFETCH;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -68,11 +71,13 @@ __global__ __launch_bounds__(GLB_NT) void chain_glb_kernel(ProblemView P, double
                                                            const int32_t *__restrict__ idx,
                                                            int64_t k0, int64_t nsteps, int rule,
                                                            int32_t *__restrict__ trace_j,
-                                                           double *__restrict__ trace_gamma)
+                                                           double *__restrict__ trace_gamma,
+                                                           int64_t *__restrict__ stats)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NT = GLB_NT, NW = NT / 64;
+    if (threadIdx.x == 0) stats[2] = SROT_CHAIN_GLOBAL;
     __shared__ double s_v[2][NW];
     __shared__ int s_j[2][NW];
     __shared__ double s_sum[2][NW][4];
@@ -195,9 +200,10 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
                                                              int64_t nsteps, int rule,
                                                              int32_t *__restrict__ trace_j,
                                                              double *__restrict__ trace_gamma,
-                                                             double delta2)
+                                                             double delta2, int64_t *__restrict__ stats)
 {
     constexpr int NW = WIDE_NT / 64;
+    if (threadIdx.x == 0) stats[2] = SROT_CHAIN_WIDE;
     extern __shared__ float r32[];
     __shared__ float s_m[2][NW];
     __shared__ double s_v[2][NW];
@@ -1318,11 +1324,11 @@ static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, 
                 if (tj || tg)                                                                      \
                     hipLaunchKernelGGL((chain_wide_kernel<CPTK_, YMODE_, true>), dim3(1), dim3(WIDE_NT), \
                                        lds, st, P, S.T, S.r, S.mask, o.words, idx, k0, nsteps, rule, tj, \
-                                       tg, S.screen_delta2);                                       \
+                                       tg, S.screen_delta2, S.slow_steps);                         \
                 else                                                                               \
                     hipLaunchKernelGGL((chain_wide_kernel<CPTK_, YMODE_, false>), dim3(1), dim3(WIDE_NT), \
                                        lds, st, P, S.T, S.r, S.mask, o.words, idx, k0, nsteps, rule, tj, \
-                                       tg, S.screen_delta2);                                       \
+                                       tg, S.screen_delta2, S.slow_steps);                         \
                 return hipGetLastError();                                                          \
             }
             SROT_WIDE(16, 1)
@@ -1332,7 +1338,7 @@ static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, 
         }
     }
     hipLaunchKernelGGL((chain_glb_kernel<COST>), dim3(1), dim3(GLB_NT), 0, st, P, S.T, S.r, S.mask,
-                       o.words, idx, k0, nsteps, rule, tj, tg);
+                       o.words, idx, k0, nsteps, rule, tj, tg, S.slow_steps);
     return hipGetLastError();
 }
 

@@ -417,6 +417,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
         if (lane == 0) {
             slow_steps[0] = n_fall;
             slow_steps[1] = n_slow;
+            slow_steps[2] = SROT_CHAIN_SCREENED;
         }
     } else if (wid == 4) {
         // shares the stepper's SIMD: keeps the barriers only
@@ -448,6 +449,17 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int col0 = (g * 256 + th) * 4;
+                // Deliberate race: the stepper wave may store to these r32
+                // entries in this same phase (plain ds_write_b32 against this
+                // ds_read_b128, no barrier between them).  The LDS carries
+                // out each dword of a DS access whole, so each value read is
+                // the FP32 residual either before or after the step being
+                // taken, never a torn word.  Either is covered: the
+                // certificate's decrease allowance counts that step among the
+                // SC_DECN steps a screen may have missed, and a value that
+                // rose since it was read only makes the screened bound
+                // smaller than the truth.  Relaxed atomic loads would state
+                // the same contract but split this read into four.
                 const float4 rr = *reinterpret_cast<const float4 *>(&r32[col0]);
                 const float rv[4] = {rr.x, rr.y, rr.z, rr.w};
 #pragma unroll

@@ -31,6 +31,10 @@ SROT_COST_F32 = 0
 SROT_COST_F64 = 1
 SROT_COST_SQEUCLID = 2
 SROT_GA_INIT = 2.0 ** 300
+SROT_CHAIN_PREFETCH = 1
+SROT_CHAIN_SCREENED = 2
+SROT_CHAIN_GLOBAL = 3
+SROT_CHAIN_WIDE = 4
 
 
 class SrotError(RuntimeError):

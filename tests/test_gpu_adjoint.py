@@ -205,6 +205,21 @@ def test_autograd_function_fused_and_stored():
     np.testing.assert_allclose(C.grad.sum(dim=1).cpu().numpy(), d["a"], rtol=1e-6)
 
 
+def test_unconverged_forward_warns():
+    """A solve that stops at max_passes with gap > eps returns the value of
+    its last plan and says so with a RuntimeWarning (its envelope gradients
+    are then only approximate)."""
+    from paper_2103_05857_amd.autograd import semi_relaxed_ot
+    d = I.problem_mixture(3, 64, 96, cost_dtype=np.float32)
+    a = torch.from_numpy(d["a"]).to(DEV)
+    b = torch.from_numpy(d["b"]).to(DEV)
+    C = torch.from_numpy(d["C"]).to(DEV).requires_grad_(True)
+    with pytest.warns(RuntimeWarning, match="no convergence"):
+        V = semi_relaxed_ot(a, b, C=C, w=10.0, eps=1e-12, max_passes=1)
+    V.backward()
+    np.testing.assert_allclose(C.grad.sum(dim=1).cpu().numpy(), d["a"], rtol=1e-6)
+
+
 def test_backward_error_paths():
     S = _S()
     d = I.problem_mixture(4, 16, 20, cost_dtype=np.float32)

@@ -85,7 +85,7 @@ def _close_fg(gpu, ref):
 
 
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("cost_mode,dtype,m,n,w", [
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w,dirichlet_b", [(*c, False)[:6] for c in [
     ("stored", np.float64, 256, 256, 1.0),     # uniform RGB, FP64 C (small config)
     ("stored", np.float32, 300, 700, 0.1),     # ragged, several tiles
     ("stored", np.float32, 333, 1500, 10.0),
@@ -96,10 +96,14 @@ def _close_fg(gpu, ref):
     ("sqeuclid", None, 23, 12001, 1.0),         # wide rows, 32 columns per thread
     ("sqeuclid", None, 11, 20000, 0.5),         # wide rows, points streamed from L2
     ("sqeuclid", None, 5, 32768, 10.0),         # the widest screened row
-])
-def test_trace_parity_explicit_indices(cost_mode, dtype, m, n, w):
+    # target weights b ~ Dirichlet(1), as in the 32768-point fused workload
+    ("sqeuclid", None, 9, 32768, 1.0, True),
+    ("sqeuclid", None, 13, 9000, 1.0, True),
+    ("stored", np.float32, 97, 4096, 1.0, True),
+]])
+def test_trace_parity_explicit_indices(cost_mode, dtype, m, n, w, dirichlet_b):
     _need_gpu()
-    d = I.problem_mixture(5, m, n, cost_dtype=dtype or np.float32)
+    d = I.problem_mixture(5, m, n, cost_dtype=dtype or np.float32, dirichlet_b=dirichlet_b)
     passes = 6
     idx = I.philox_uniform_indices(21, 0, passes * m, m)
     P = _oracle_problem(d, cost_mode, w)
@@ -107,8 +111,16 @@ def test_trace_parity_explicit_indices(cost_mode, dtype, m, n, w):
     otr = O.bcfw_steps(P, st, idx, rule=O.ELS)
     ref = O.gap(P, st.T)
 
+    S = _S()
     sol = _gpu_problem(d, cost_mode, w)
     gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
+    kind = S.srot_chain_stats(sol.h)[2]
+    if n > 4096:
+        assert kind == (S.SROT_CHAIN_WIDE if cost_mode == "sqeuclid" else S.SROT_CHAIN_GLOBAL)
+    elif cost_mode == "stored" and dtype == np.float32 and n > 512 and n % 4 == 0:
+        assert kind == S.SROT_CHAIN_SCREENED
+    else:
+        assert kind == S.SROT_CHAIN_PREFETCH
     _compare_traces(otr, gj, gg)
     _close_fg(sol.gap(), ref)
     T, r = sol.plan()

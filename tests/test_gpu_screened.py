@@ -82,6 +82,7 @@ def test_screened_traces_match_oracle(m, n, w, rule, passes):
     sol = _solver(d, w, step_rule=(S.SROT_ELS if rule == "els" else S.SROT_DEC))
     gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
     stats = S.srot_chain_stats(sol.h)
+    assert stats[2] == S.SROT_CHAIN_SCREENED     # the screened kernel took these steps
     _compare(otr, gj, gg)
     _check_plan(sol, st, d)
     if m <= 6:
@@ -103,7 +104,8 @@ def test_unscreened_chain_on_the_same_problem():
     otr = O.bcfw_steps(P, st, idx)
     sol = _solver(d, w, screen=False)
     gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
-    assert S.srot_chain_stats(sol.h)[1] == 0
+    stats = S.srot_chain_stats(sol.h)
+    assert stats[1] == 0 and stats[2] == S.SROT_CHAIN_PREFETCH
     _compare(otr, gj, gg)
     _check_plan(sol, st, d)
     sol.close()
@@ -134,7 +136,8 @@ def test_rows_with_more_nonzeros_per_lane_than_prepared():
     sol = _solver(d, w)
     sol.set_state(torch.from_numpy(T).to(DEV), 0)
     gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
-    assert S.srot_chain_stats(sol.h)[1] >= 16
+    stats = S.srot_chain_stats(sol.h)
+    assert stats[1] >= 16 and stats[2] == S.SROT_CHAIN_SCREENED
     _compare(otr, gj, gg)
     _check_plan(sol, st, d)
     sol.close()
@@ -180,7 +183,7 @@ def test_exact_ties_in_one_lane_fall_back_to_the_full_row():
             checked += 1
         touched.add(int(otr[0][k]))
     assert checked > 0
-    assert stats[0] > 0
+    assert stats[0] > 0 and stats[2] == S.SROT_CHAIN_SCREENED
     sol.close()
 
 
@@ -198,6 +201,7 @@ def test_solve_to_gap_with_the_screened_chain():
     sol = _solver(d, w, seed=4, eps=eps, max_passes=1500)
     status, (g, f, D), passes = sol.solve()
     assert status == S.SROT_OK and g <= eps
+    assert S.srot_chain_stats(sol.h)[2] == S.SROT_CHAIN_SCREENED
     assert abs((f - D) - g) <= 1e-12
     T, r = sol.plan()
     T = T.cpu().numpy()
@@ -227,6 +231,7 @@ def test_permutation_sampling_on_the_screened_chain():
         gj, gg = sol.step(c, trace=True)
         gjs.append(gj)
         ggs.append(gg)
+    assert S.srot_chain_stats(sol.h)[2] == S.SROT_CHAIN_SCREENED
     _compare(otr, torch.cat(gjs), torch.cat(ggs))
     _check_plan(sol, st, d)
     sol.close()
@@ -236,11 +241,13 @@ def test_zero_penalty_closed_form_on_the_screened_chain():
     """w = 0: every block step moves its row to a_i at the row's smallest
     cost, lowest column on ties (the closed form of the zero-penalty limit),
     whatever the residual; one pass in a random order reaches it exactly."""
+    S = _S()
     m, n = 200, 2048
     d = I.problem_mixture(44, m, n)
     sol = _solver(d, 0.0)
     perm = np.random.default_rng(1).permutation(m).astype(np.int32)
     sol.step(m, idx=torch.from_numpy(perm).to(DEV))
+    assert S.srot_chain_stats(sol.h)[2] == S.SROT_CHAIN_SCREENED
     T, _ = sol.plan()
     Texp = np.zeros((m, n))
     Texp[np.arange(m), np.argmin(d["C"], axis=1)] = d["a"]

@@ -358,3 +358,43 @@ def test_fw_iteration_gap_and_line_search():
         np.testing.assert_allclose(T2, (1 - gam) * T + gam * S, atol=1e-15)
         fvals = [objective_np(C, a, b, w, (1 - g) * T + g * S) for g in grid]
         assert objective_np(C, a, b, w, T2) <= min(fvals) + 1e-14
+
+
+def test_fw_iteration_decay_rule():
+    """Decay rule of Alg. A.1, gamma_k = 2/(k+2), pinned by a closed form: at
+    w = 0 the LMO vertex S (every row at its cheapest column) does not depend
+    on T, so the first iteration (k = 0, gamma = 1) lands on S exactly, and
+    from any T_1 the iterations k = 1..K-1 shrink T - S by the telescoping
+    product prod_k k/(k+2) = 2/(K(K+1)).  The gap returned before each step
+    is then <T_k - S, C> = 2/(k(k+1)) <T_1 - S, C>.  A misread counter
+    (2/(k+1), 2/(k+3), a counter of block steps) breaks both."""
+    rng = np.random.default_rng(16)
+    m, n = 5, 7
+    C, a, b, P = _problem(rng, m, n, 0.0)
+    S = np.zeros((m, n)); S[np.arange(m), np.argmin(C, axis=1)] = a
+    T = _rand_plan(rng, a, n)
+    T0 = T.copy()
+    g0, gam = O.fw_iteration(P, T, 0, rule=O.DEC)
+    assert gam == 1.0
+    np.testing.assert_array_equal(T, S)
+    assert abs(g0 - float(np.sum((T0 - S) * C))) <= 1e-14
+    T = T0.copy()
+    g1 = float(np.sum((T0 - S) * C))
+    for k in range(1, 12):
+        gk, gam = O.fw_iteration(P, T, k, rule=O.DEC)
+        assert abs(gk - 2.0 / (k * (k + 1)) * g1) <= 1e-14
+        K = k + 1
+        np.testing.assert_allclose(T, S + 2.0 / (K * (K + 1)) * (T0 - S), rtol=0, atol=1e-15)
+    # w > 0: the LMO vertex moves with r; the step is still the decay step
+    # towards the brute-force LMO vertex of the current plan
+    C, a, b, P = _problem(rng, m, n, 2.5)
+    T = _rand_plan(rng, a, n)
+    for k in range(0, 6):
+        r = T.sum(axis=0) - b
+        G = C + 2.5 * r[None, :]
+        Sk = np.zeros((m, n)); Sk[np.arange(m), np.argmin(G, axis=1)] = a
+        T_before = T.copy()
+        gk, gam = O.fw_iteration(P, T, k, rule=O.DEC)
+        assert gam == 2.0 / (k + 2.0)
+        assert abs(gk - float(np.sum((T_before - Sk) * G))) <= 1e-13
+        np.testing.assert_allclose(T, (1 - gam) * T_before + gam * Sk, rtol=0, atol=1e-15)

@@ -124,3 +124,42 @@ def test_reaches_the_bruteforce_optimum(variant, seed, m, n, w):
     O.active_steps(P, st, I.philox_uniform_indices(seed, 0, 400 * m, m), variant, trace=False)
     fstar, _ = kkt_bruteforce(C, a, b, w)
     assert O.objective(P, st.T) - fstar <= 1e-12
+
+
+def test_away_direction_choice_margin_is_the_slope_difference():
+    """BCAFW (Alg. A.2) takes the FW direction when its descent slope is at
+    least the away direction's.  The oracle reports the margin of that choice,
+    <-g, d_FW> - <-g, d_A>; here each slope is measured as a central
+    difference of f along the direction (exact up to rounding, f being
+    quadratic), and the direction taken must follow the sign of the margin."""
+    d = I.problem_mixture(21, 10, 8, cost_dtype=np.float64)
+    C, a, b, w = d["C"], d["a"], d["b"], 2.0
+    P, st = _state_after_bcfw(d, w, 50)
+    rng = np.random.default_rng(4)
+    choices = set()
+    checked = 0
+    for i in rng.integers(0, 10, 120):
+        i = int(i)
+        T0 = st.T.copy()
+        sup = np.nonzero(T0[i] > 0)[0]
+        tr = O.active_steps(P, st, np.array([i], np.int32), O.AWAY)
+        js = int(tr["j"][0])
+        ja = int(tr["away"][0]) if tr["away"][0] >= 0 else -1 - int(tr["away"][0])
+        if len(sup) == 1 or ja == js:
+            assert np.isnan(tr["dslope"][0]) and tr["away"][0] < 0
+            continue
+        s = np.zeros(8); s[js] = a[i]
+        v = np.zeros(8); v[ja] = a[i]
+        h = 1e-3
+        slopes = []
+        for dvec in (s - T0[i], T0[i] - v):
+            Tp, Tm = T0.copy(), T0.copy()
+            Tp[i] += h * dvec
+            Tm[i] -= h * dvec
+            slopes.append(-(objective_np(C, a, b, w, Tp) - objective_np(C, a, b, w, Tm)) / (2 * h))
+        assert abs(tr["dslope"][0] - (slopes[0] - slopes[1])) <= 1e-10
+        took_fw = tr["away"][0] < 0
+        assert took_fw == (tr["dslope"][0] >= 0.0)
+        choices.add(took_fw)
+        checked += 1
+    assert checked >= 40 and choices == {True, False}
