@@ -181,10 +181,10 @@ def test_autograd_function_fused_and_stored():
     b = torch.from_numpy(d["b"]).to(DEV).requires_grad_(True)
     X = torch.from_numpy(d["X"]).to(DEV).requires_grad_(True)
     Y = torch.from_numpy(d["Y"]).to(DEV).requires_grad_(True)
-    V = semi_relaxed_ot(a, b, X=X, Y=Y, w=1.0, eps=1e-8, max_passes=3000)
+    V = semi_relaxed_ot(a, b, X=X, Y=Y, w=1.0, eps=1e-6, max_passes=3000)
     (2.0 * V).backward()
     # same run through the plain solver: same plan (deterministic), then the oracle formulas
-    sol = _solver(d, "sqeuclid", 1.0, eps=1e-8, max_passes=3000)
+    sol = _solver(d, "sqeuclid", 1.0, eps=1e-6, max_passes=3000)
     _, (g, f, D), _ = sol.solve()
     T, _ = sol.plan()
     T = T.cpu().numpy()
@@ -198,7 +198,7 @@ def test_autograd_function_fused_and_stored():
     assert _rel(b.grad.cpu().numpy(), ref["db"]) <= 1e-13
 
     C = torch.from_numpy(d["C"]).to(DEV).requires_grad_(True)
-    V2 = semi_relaxed_ot(a.detach(), b.detach(), C=C, w=1.0, eps=1e-8, max_passes=3000)
+    V2 = semi_relaxed_ot(a.detach(), b.detach(), C=C, w=1.0, eps=1e-6, max_passes=3000)
     V2.backward()
     assert C.grad.dtype == torch.float32
     assert torch.all(C.grad >= 0)
