@@ -215,6 +215,31 @@ int srot_chain_stats(srot_handle *h, int64_t *out4);
 int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *dY,
                   double *da, double *db);
 
+/* srot_backward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs (bit for bit) and errors as srot_backward, and it
+ * calls no hipMalloc, hipFree or allocating library routine.  The scratch
+ * of its kernels -- the gap sweep's arrival counter, per-workgroup partial
+ * sums and final sums (when da is requested) and the per-row-slice column
+ * sums of dY -- is not taken from the workspace but from a static device
+ * array of SROT_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends; its address is looked up at srot_init with
+ * the handle's device current.  All calls on one GPU share that array and
+ * it keeps the last call's contents (the counter is cleared by a kernel at
+ * every call): calls that overlap on one GPU (several streams or threads)
+ * race and give wrong results, so serialise them.  The handle's per-row gap
+ * arrays are updated as srot_backward updates them.
+ * Limit: 512 bytes, plus 64 x min(2048, ceil(m / 8)) bytes with da, plus
+ * 24 n s bytes with dY (s <= min(m, 32) row slices) must fit in
+ * SROT_NOALLOC_SCRATCH_BYTES; with every output that holds for any m when
+ * n <= 10751.
+ * Errors: those of srot_backward; SROT_EINVAL when the scratch needed
+ * exceeds the limit (srot_backward has none); SROT_EHIP when the static
+ * array had no device address at srot_init. */
+#define SROT_NOALLOC_SCRATCH_BYTES (8u << 20)
+int srot_backward_noalloc(srot_handle *h, double grad_out, void *dC, float *dX, float *dY,
+                          double *da, double *db);
+
 /* Block steps with away or pairwise directions (Sec. 4.1, Alg. A.2 / A.3)
  * on the handle's plan, in place of srot_step's FW direction.  A row's
  * active set is its support; per step, with g = c_i + w r:

@@ -266,6 +266,24 @@ hipError_t launch_barycentric(const ProblemView &P, const DeviceState &S, float 
 
 int32_t adjoint_slices_cap(int64_t m) { return (int32_t)std::min<int64_t>(m, 32); }
 
+// Row slices of the dY column sums: enough (slice x column-group)
+// workgroups to fill the chip, at most adjoint_slices_cap(m).
+static int adjoint_slices(const ProblemView &P, const Ownership &own, int *rows_per_slice)
+{
+    const int slots = own.words * own.nt;
+    const int gx = (slots + 63) / 64;
+    const int want = std::max(1, (1024 + gx - 1) / gx);
+    const int cap = adjoint_slices_cap(P.m);
+    const int rps = (int)((P.m + std::min(want, cap) - 1) / std::min(want, cap));
+    if (rows_per_slice) *rows_per_slice = rps;
+    return (int)((P.m + rps - 1) / rps);
+}
+
+size_t adjoint_part_doubles(const ProblemView &P, const Ownership &own)
+{
+    return (size_t)adjoint_slices(P, own, nullptr) * 3 * (size_t)P.n;
+}
+
 hipError_t launch_adjoint(const ProblemView &P, const DeviceState &S, double g, void *dC,
                           float *dX, float *dY, double *da, double *db, hipStream_t stream)
 {
@@ -285,10 +303,8 @@ hipError_t launch_adjoint(const ProblemView &P, const DeviceState &S, double g, 
     if (dY) {
         const int slots = own.words * own.nt;
         const int gx = (slots + 63) / 64;
-        const int want = std::max(1, (1024 + gx - 1) / gx);
-        const int cap = adjoint_slices_cap(P.m);
-        const int rows_per_slice = (int)((P.m + std::min(want, cap) - 1) / std::min(want, cap));
-        slices = (int)((P.m + rows_per_slice - 1) / rows_per_slice);
+        int rows_per_slice = 1;
+        slices = adjoint_slices(P, own, &rows_per_slice);
         hipLaunchKernelGGL(adjoint_cols_kernel, dim3(gx, slices), dim3(ADJ_NT), 0, stream, P,
                            (const double *)S.T, (const uint32_t *)S.mask, own, rows_per_slice,
                            S.adj_part);

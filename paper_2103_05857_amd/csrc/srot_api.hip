@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/srot.h"
@@ -20,7 +21,48 @@ struct srot_handle {
     hipStream_t stream;
     int64_t k;     // global block-step counter (decay rule, sampler position)
     int64_t fw_k;  // full Frank-Wolfe iteration counter (decay rule of Alg. A.1)
+    void *scratch;            // this device's copy of `scratch` (below), or null
+    hipError_t scratch_err;   // why `scratch` is null
 };
+
+// Scratch of srot_backward_noalloc: one copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, never a device
+// address: host code uses only the address hipGetSymbolAddress returns for
+// the current device (kept per device below, and per handle).
+static __device__ __align__(256) unsigned char scratch[SROT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+// Zeroes the control words of the static scratch (the gap sweep's arrival
+// counter must start at zero): a kernel, so the call stays capturable.
+__global__ void noalloc_clear_kernel(int32_t *words)
+{
+    if (threadIdx.x < 64) words[threadIdx.x] = 0;
+}
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.
+hipError_t scratch_address(void **out)
+{
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 thread_local std::string g_last_error;
@@ -307,6 +349,9 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     else if (flag & 1) rc = fail(SROT_ENONFINITE, "srot_init: NaN/Inf in C, X, Y, a or b, or a negative weight");
     h->S.screen_delta2 = 0.0;
     h->S.screen_err = 0.0;
+    // the allocation-free backward's scratch on this device (its absence
+    // only disables srot_backward_noalloc)
+    if (rc == SROT_OK) h->scratch_err = scratch_address(&h->scratch);
     if (rc == SROT_OK && screened) {
         // FP32 screen value fma(w, r, c) against c + w r: at most 2^-22
         // (|c| + |w| |r|) off (rounding of r, w and the fma); doubled
@@ -438,6 +483,45 @@ int srot_backward(srot_handle *h, double grad_out, void *dC, float *dX, float *d
         return fail(SROT_EINVAL, "srot_backward: dX and dY need the points X and Y given to srot_init");
     if (da) SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));  // row minima of the gradient
     SROT_HIP(srot::launch_adjoint(h->P, h->S, grad_out, dC, dX, dY, da, db, h->stream));
+    return SROT_OK;
+}
+
+int srot_backward_noalloc(srot_handle *h, double grad_out, void *dC, float *dX, float *dY, double *da,
+                          double *db)
+{
+    if (!h) return fail(SROT_EINVAL, "srot_backward_noalloc: NULL handle");
+    if (!isfinite(grad_out)) return fail(SROT_EINVAL, "srot_backward_noalloc: grad_out is not finite");
+    if (dC && h->P.cost == SROT_COST_SQEUCLID)
+        return fail(SROT_EINVAL, "srot_backward_noalloc: dC needs a stored cost (the fused cost has no C)");
+    if ((dX || dY) && (!h->P.X || !h->P.Y))
+        return fail(SROT_EINVAL, "srot_backward_noalloc: dX and dY need the points X and Y given to srot_init");
+    if (!h->scratch)
+        return fail(SROT_EHIP, "srot_backward_noalloc: no static scratch on this device: %s",
+                    hipGetErrorString(h->scratch_err));
+    // layout: 64 control words (the gap sweep's arrival counter at [4]),
+    // 8 final sums, the gap sweep's per-workgroup partial sums (da), the
+    // per-row-slice column sums of dY
+    constexpr size_t kCtl = 0, kSums = 256, kPart = 512;
+    const size_t part_bytes = da ? sizeof(double) * 8 * (size_t)h->S.gap_blocks : 0;
+    const size_t adj_off = align_up(kPart + part_bytes);
+    const size_t adj_bytes = dY ? sizeof(double) * srot::adjoint_part_doubles(h->P, h->S.own) : 0;
+    if (adj_off + adj_bytes > (size_t)SROT_NOALLOC_SCRATCH_BYTES)
+        return fail(SROT_EINVAL,
+                    "srot_backward_noalloc: needs %zu bytes of scratch (m=%d, n=%d), above its static %zu; "
+                    "use srot_backward", adj_off + adj_bytes, h->P.m, h->P.n, (size_t)SROT_NOALLOC_SCRATCH_BYTES);
+    srot::DeviceState S = h->S;
+    char *base = (char *)h->scratch;
+    S.flags = (int32_t *)(base + kCtl);
+    S.scalars = (double *)(base + kSums);
+    S.partials = (double *)(base + kPart);
+    S.adj_part = (double *)(base + adj_off);
+    if (da) {
+        // the row minima of the gradient, as srot_backward
+        hipLaunchKernelGGL(noalloc_clear_kernel, dim3(1), dim3(64), 0, h->stream, S.flags);
+        SROT_HIP(hipGetLastError());
+        SROT_HIP(srot::launch_gap(h->P, S, h->stream));
+    }
+    SROT_HIP(srot::launch_adjoint(h->P, S, grad_out, dC, dX, dY, da, db, h->stream));
     return SROT_OK;
 }
 

@@ -119,6 +119,8 @@ hipError_t launch_adjoint(const ProblemView &P, const DeviceState &S, double g, 
                           float *dX, float *dY, double *da, double *db, hipStream_t stream);
 // Row slices of the adjoint's column sums (sizes DeviceState::adj_part).
 int32_t adjoint_slices_cap(int64_t m);
+// doubles of per-slice dY column sums (adj_part) that launch_adjoint uses
+size_t adjoint_part_doubles(const ProblemView &P, const Ownership &own);
 
 // Full Frank-Wolfe iteration (srot_fw.hip): launch_fw_update runs the vertex
 // column sums, the step size (scalars[5]) and the update after a gap sweep;

@@ -35,6 +35,7 @@ SROT_CHAIN_PREFETCH = 1
 SROT_CHAIN_SCREENED = 2
 SROT_CHAIN_GLOBAL = 3
 SROT_CHAIN_WIDE = 4
+SROT_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class SrotError(RuntimeError):
@@ -88,6 +89,8 @@ def load():
     L.srot_chain_stats.restype = ctypes.c_int
     L.srot_backward.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
     L.srot_backward.restype = ctypes.c_int
+    L.srot_backward_noalloc.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+    L.srot_backward_noalloc.restype = ctypes.c_int
     L.srot_workspace_size_batched.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.POINTER(srot_options)]
     L.srot_workspace_size_batched.restype = ctypes.c_size_t
     L.srot_init_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -233,6 +236,13 @@ def srot_chain_stats(h):
 def srot_backward(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):
     _check(load().srot_backward(h, float(grad_out), _ptr(dC, (_F32, _F64)), _ptr(dX, _F32), _ptr(dY, _F32),
                                 _ptr(da, _F64), _ptr(db, _F64)))
+
+
+def srot_backward_noalloc(h, grad_out, dC=None, dX=None, dY=None, da=None, db=None):
+    """srot_backward with its scratch in the library's static device array
+    (no allocation, no workspace scratch)."""
+    _check(load().srot_backward_noalloc(h, float(grad_out), _ptr(dC, (_F32, _F64)), _ptr(dX, _F32),
+                                        _ptr(dY, _F32), _ptr(da, _F64), _ptr(db, _F64)))
 
 
 def srot_fw_steps(h, iters, trace_gamma=None):

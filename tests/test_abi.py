@@ -94,6 +94,8 @@ def test_null_handle_is_rejected():
     assert L.srot_ga_weights(None, None) == S.SROT_EINVAL
     stats = (ctypes.c_int64 * 4)()
     assert L.srot_chain_stats(None, stats) == S.SROT_EINVAL
+    assert L.srot_backward(None, 1.0, None, None, None, None, None) == S.SROT_EINVAL
+    assert L.srot_backward_noalloc(None, 1.0, None, None, None, None, None) == S.SROT_EINVAL
     assert L.srot_strerror(S.SROT_ENONFINITE) == b"non-finite or negative input"
 
 
