@@ -222,9 +222,16 @@ def bench_sweep(args):
     a = torch.from_numpy(d["a"]).to(dev)
     b = torch.from_numpy(d["b"]).to(dev)
     sol = S.Solver(a, b, C=C, w=1.0, seed=0)
-    S.srot_step(sol.h, n)
-    out5 = torch.empty(5, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    # one pass of block steps on the stored 16384-column rows (the team chain)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    S.srot_step(sol.h, n)
+    c1.record(stream)
+    c1.synchronize()
+    chain_us = 1000.0 * c0.elapsed_time(c1) / n
+    out5 = torch.empty(5, dtype=torch.float64, device=dev)
     for _ in range(3):
         S.srot_gap_async(sol.h, out5)
     torch.cuda.synchronize()
@@ -249,7 +256,8 @@ def bench_sweep(args):
             "kernel": "gap_stream_kernel<f32,2,2> (+ 40-byte readback copy)", "bound": "hbm",
             "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS,
-            "traffic": counter_traffic("srot::gap_stream_kernel<0, 2, 2>", SWEEP_PROFILE, grid=2048 * 256)}
+            "traffic": counter_traffic("srot::gap_stream_kernel<0, 2, 2>", SWEEP_PROFILE, grid=2048 * 256),
+            "chain_us_per_block_update_first_pass": chain_us}
 
 
 def bench_fw(args, C, a, b):

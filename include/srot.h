@@ -176,7 +176,9 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
  *            nonzeros per screener lane than prepared);
  *   out4[2]  which chain kernel ran the last launch, written by the kernel
  *            itself: SROT_CHAIN_PREFETCH, SROT_CHAIN_SCREENED,
- *            SROT_CHAIN_GLOBAL or SROT_CHAIN_WIDE (0 before any launch);
+ *            SROT_CHAIN_TEAM (the default beyond 4096 columns), or
+ *            SROT_CHAIN_GLOBAL / SROT_CHAIN_WIDE (one workgroup, selected by
+ *            SROT_TEAM_CHAIN=0 in the environment) (0 before any launch);
  *   out4[3]  0 (reserved).
  * The chains for rows of up to 4096 columns with a register-resident
  * residual write out4[0] and out4[1] at every launch; the wide-row chains
@@ -188,7 +190,8 @@ int srot_chain_stats(srot_handle *h, int64_t *out4);
 #define SROT_CHAIN_PREFETCH  1   /* one workgroup, rows prefetched, r in LDS   */
 #define SROT_CHAIN_SCREENED  2   /* stepper wave over FP32-screened candidates */
 #define SROT_CHAIN_GLOBAL    3   /* stored cost wider than 4096 columns        */
-#define SROT_CHAIN_WIDE      4   /* fused cost wider than 4096 columns         */
+#define SROT_CHAIN_WIDE      4   /* fused cost wider than 4096 columns (one workgroup) */
+#define SROT_CHAIN_TEAM      5   /* rows of 4097-65536 columns over a team of workgroups */
 
 /* Gradients of the optimal value V = min f (the problem above) with respect
  * to the inputs, evaluated at the handle's current plan T and scaled by

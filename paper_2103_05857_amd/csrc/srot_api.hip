@@ -95,7 +95,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, slow, Y4, adj, ga_w, total;
+    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, slow, Y4, adj, ga_w, team, total;
     int64_t idx_cap;
     int32_t gap_blocks;
 };
@@ -137,6 +137,8 @@ Layout make_layout(int64_t m, int64_t n)
     L.Y4 = off; off = align_up(off + 16 * (size_t)srot::y4_entries(n));
     L.adj = off; off = align_up(off + sizeof(double) * 3 * (size_t)n * (size_t)srot::adjoint_slices_cap(m));
     L.ga_w = off; off = align_up(off + sizeof(double) * (size_t)m);
+    L.team = off;
+    off = align_up(off + sizeof(unsigned long long) * 2 * srot::TEAM_MAX_MEMBERS * srot::TEAM_REC_STRIDE);
     L.total = off;
     return L;
 }
@@ -235,8 +237,14 @@ int measure_gap(srot_handle *h, double *out3)
 {
     SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
     double host[3];
+    int32_t team_err = 0;
     SROT_HIP(hipMemcpyAsync(host, h->S.scalars, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+    if (h->S.team)
+        SROT_HIP(hipMemcpyAsync(&team_err, h->S.flags + 6, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     SROT_HIP(hipStreamSynchronize(h->stream));
+    if (team_err)
+        return fail(SROT_EHIP, "team chain: a member waited too long for the others' records; "
+                               "the plan and residual are inconsistent");
     out3[0] = host[0]; out3[1] = host[1]; out3[2] = host[2];
     return SROT_OK;
 }
@@ -321,6 +329,8 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->S.slow_steps = (int64_t *)(base + L.slow);
     h->S.adj_part = (double *)(base + L.adj);
     h->S.ga_w = (double *)(base + L.ga_w);
+    h->S.team_rec = (unsigned long long *)(base + L.team);
+    h->S.team = srot::team_chain_supported(h->P) ? 1 : 0;
 
     int rc = SROT_OK;
     int32_t flag = 0;

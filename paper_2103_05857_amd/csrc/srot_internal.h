@@ -53,6 +53,8 @@ struct DeviceState {
     int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW ticket
     int64_t *slow_steps;   // 4: slow-path step counts of the last chain launch (diagnostic)
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
+    unsigned long long *team_rec;  // 2 x TEAM_MAX_MEMBERS x TEAM_REC_STRIDE exchange words of the team chain
+    int32_t team;          // 1: block steps run on the team chain (chosen at init)
     double screen_delta2;  // 2 x error bound of the FP32 LMO screen (wide fused rows), 0 = unused
     double screen_err;     // error bound of the FP32 LMO screen of the screened chain, 0 = chain unused
     double *ga_w;          // m, stored block gaps of the gap-adaptive sampler
@@ -111,6 +113,17 @@ inline int64_t y4_entries(int64_t n)
 
 // Number of workgroups used by the gap sweep for an m-row problem.
 int32_t gap_blocks_for(int64_t m);
+
+// Block-step chain over a team of workgroups (srot_team.hip), rows of
+// 4097 .. 1024 * TEAM_MAX_MEMBERS columns, any cost; the default there
+// unless SROT_TEAM_CHAIN=0 is set in the environment at init.
+constexpr int TEAM_MAX_MEMBERS = 64;
+constexpr int TEAM_REC_STRIDE = 16;  // 64-bit words per member record (one 128-byte line)
+int team_members(int64_t n);
+bool team_chain_supported(const ProblemView &P);
+hipError_t launch_chain_team(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t k0,
+                             int64_t nsteps, int rule, int32_t *trace_j, double *trace_gamma,
+                             hipStream_t stream);
 
 // Adjoint at the current plan (srot_adjoint.hip): dC (m x n, float or double
 // as the stored cost), dX (m x 3), dY (n x 3), da (m, reads row_G of the last

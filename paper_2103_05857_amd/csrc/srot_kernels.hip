@@ -1311,6 +1311,7 @@ static hipError_t launch_chain_cost(const ProblemView &P, const DeviceState &S, 
 #undef SROT_CHAIN
         return hipErrorInvalidConfiguration;
     }
+    if (S.team) return launch_chain_team(P, S, idx, k0, nsteps, rule, tj, tg, st);
     if constexpr (COST == SROT_COST_SQEUCLID) {
         if (P.n <= WIDE_MAX_N && S.screen_delta2 > 0.0) {
             const size_t lds = sizeof(float) * (size_t)WIDE_NT * (o.cpt <= 16 ? 16 : (o.cpt <= 32 ? 32 : 64));

@@ -35,6 +35,7 @@ SROT_CHAIN_PREFETCH = 1
 SROT_CHAIN_SCREENED = 2
 SROT_CHAIN_GLOBAL = 3
 SROT_CHAIN_WIDE = 4
+SROT_CHAIN_TEAM = 5
 SROT_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 

@@ -116,7 +116,7 @@ def test_trace_parity_explicit_indices(cost_mode, dtype, m, n, w, dirichlet_b):
     gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
     kind = S.srot_chain_stats(sol.h)[2]
     if n > 4096:
-        assert kind == (S.SROT_CHAIN_WIDE if cost_mode == "sqeuclid" else S.SROT_CHAIN_GLOBAL)
+        assert kind == S.SROT_CHAIN_TEAM
     elif cost_mode == "stored" and dtype == np.float32 and n > 512 and n % 4 == 0:
         assert kind == S.SROT_CHAIN_SCREENED
     else:
@@ -129,6 +129,70 @@ def test_trace_parity_explicit_indices(cost_mode, dtype, m, n, w, dirichlet_b):
     assert T.min() >= 0.0
     np.testing.assert_allclose(T.sum(axis=1), d["a"], rtol=1e-12)
     np.testing.assert_allclose(r.cpu().numpy(), T.sum(axis=0) - d["b"], rtol=0, atol=1e-13)
+
+
+def _trace_case(d, cost_mode, w, idx, rule=O.ELS, **opts):
+    """Runs idx on both sides and applies the block-step bar; returns the
+    solver (open) and the oracle state."""
+    S = _S()
+    P = _oracle_problem(d, cost_mode, w)
+    st = O.State(P)
+    otr = O.bcfw_steps(P, st, idx, rule=rule)
+    sol = _gpu_problem(d, cost_mode, w, step_rule=(S.SROT_DEC if rule == O.DEC else S.SROT_ELS), **opts)
+    gj, gg = sol.step(len(idx), idx=torch.from_numpy(idx).to(DEV), trace=True)
+    _compare_traces(otr, gj, gg)
+    _close_fg(sol.gap(), O.gap(P, st.T))
+    T, r = sol.plan()
+    T = T.cpu().numpy()
+    np.testing.assert_allclose(T, st.T, rtol=1e-9, atol=1e-12)
+    assert T.min() >= 0.0
+    np.testing.assert_allclose(T.sum(axis=1), d["a"], rtol=1e-12)
+    np.testing.assert_allclose(r.cpu().numpy(), T.sum(axis=0) - d["b"], rtol=0, atol=1e-13)
+    return sol, st
+
+
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w,rule,passes", [
+    ("sqeuclid", None, 3, 9000, 1.0, O.ELS, 60),        # 3 rows: revisits inside the prefetch window
+    ("stored", np.float32, 4, 4097, 2.0, O.ELS, 40),    # one column past 4096: a member with one live column
+    ("stored", np.float64, 7, 6000, 0.5, O.ELS, 20),    # FP64 stored cost, ragged last member
+    ("sqeuclid", None, 5, 65536, 1.0, O.ELS, 6),        # the widest team (64 members)
+    ("sqeuclid", None, 17, 12000, 3.0, O.DEC, 8),       # decay rule
+    ("stored", np.float32, 2, 5000, 10.0, O.ELS, 150),  # two rows, strong penalty: supports over members
+])
+def test_team_chain_traces_match_oracle(cost_mode, dtype, m, n, w, rule, passes):
+    """Rows wider than 4096 columns take the team chain (workgroups of 1024
+    columns exchanging one record per step): the block-step bar on its
+    corner cases, and the support masks it maintains with atomics match
+    the plan (the gap sweep reads the plan through them)."""
+    _need_gpu()
+    S = _S()
+    d = I.problem_mixture(31, m, n, cost_dtype=dtype or np.float32, dirichlet_b=(m == 17))
+    idx = I.philox_uniform_indices(13, 0, passes * m, m)
+    sol, st = _trace_case(d, cost_mode, w, idx, rule=rule)
+    assert S.srot_chain_stats(sol.h)[2] == S.SROT_CHAIN_TEAM
+    if m <= 4:
+        assert (st.T > 0).sum(axis=1).max() >= 3        # several atoms per row were exercised
+    sol.close()
+
+
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w", [
+    ("stored", np.float32, 41, 5000, 1.0),
+    ("sqeuclid", None, 11, 20000, 0.5),
+])
+def test_one_workgroup_wide_chains(cost_mode, dtype, m, n, w):
+    """SROT_TEAM_CHAIN=0 at init keeps the one-workgroup chains for wide rows
+    (global residual for stored costs, FP32-screened for fused ones)."""
+    _need_gpu()
+    S = _S()
+    d = I.problem_mixture(5, m, n, cost_dtype=dtype or np.float32)
+    idx = I.philox_uniform_indices(21, 0, 4 * m, m)
+    os.environ["SROT_TEAM_CHAIN"] = "0"
+    try:
+        sol, _ = _trace_case(d, cost_mode, w, idx)
+    finally:
+        del os.environ["SROT_TEAM_CHAIN"]
+    assert S.srot_chain_stats(sol.h)[2] == (S.SROT_CHAIN_WIDE if cost_mode == "sqeuclid" else S.SROT_CHAIN_GLOBAL)
+    sol.close()
 
 
 def test_small_config_500_passes_internal_sampler():
