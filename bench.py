@@ -23,10 +23,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS_SRC = [os.path.join(ROOT, "paper_2103_05857_amd", "csrc", f)
-               for f in ("srot_kernels.hip", "srot_device.h", "srot_screen.hip")]
+FP64_PEAK_GFLOPS = 78600.0      # MI355X dense FP64 vector
+FP32_PEAK_GFLOPS = 157300.0     # MI355X dense FP32 vector
+CSRC = os.path.join(ROOT, "paper_2103_05857_amd", "csrc")
+KERNELS_SRC = [os.path.join(CSRC, f) for f in ("srot_kernels.hip", "srot_device.h", "srot_screen.hip")]
+FUSED_SRC = [os.path.join(CSRC, f) for f in ("srot_team.hip", "srot_kernels.hip", "srot_device.h")]
 PROFILE = os.path.join(ROOT, "profiles", "chain_gap_stored_f32_m4096_n4096.md")
 SWEEP_PROFILE = os.path.join(ROOT, "profiles", "gap_sweep_stored_f32_m16384_n16384.md")
+FUSED_PROFILE = os.path.join(ROOT, "profiles", "chain_gap_fused_m32768_n32768.md")
+
+
+def profile_counters(profile, sources, kernel_prefix):
+    """Per-dispatch counters of a kernel from a committed rocprofv3 summary,
+    or None when the summary is absent or its kernels changed since."""
+    import hashlib
+    import re
+    try:
+        text = open(profile).read()
+        blob = json.loads(re.findall(r"```json\n(.*?)\n```", text, flags=re.S)[-1])
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()[:16]
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("kernels_sha256") != sha:
+        return None
+    for name, v in blob["per_dispatch"].items():
+        if name.startswith(kernel_prefix):
+            return dict(v, fetch_scale=blob.get("fetch_scale"), write_scale=blob.get("write_scale"))
+    return None
+
+
+def fp64_counted_flops(c):
+    """FP64 flops of one dispatch from the VALU instruction counters (64 lanes
+    per instruction, an FMA counting two)."""
+    if not c or "SQ_INSTS_VALU_FMA_F64" not in c:
+        return None
+    return 64.0 * (2.0 * c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"])
 
 
 def counter_traffic(kernel_prefix, profile=PROFILE, grid=None):
@@ -424,7 +455,10 @@ def bench_diff(args):
 def bench_fused(args):
     """Fused on-the-fly cost: m = n = 32768 mixture points (the cost, 4 GiB in
     FP32, is never stored), a uniform, b ~ Dirichlet(1), w = 1, run to gap
-    1e-5 or the time cap."""
+    1e-5 or the time cap.  Rooflines against the FP64 vector peak (the chain
+    and the sweep evaluate every cost entry in FP64): algorithmic flops per
+    launch over the event-timed launch, with the counted flops and the VALU
+    share from the committed rocprofv3 summary."""
     import torch
     from paper_2103_05857_amd import inputs as I
     from paper_2103_05857_amd import srot as S
@@ -441,6 +475,8 @@ def bench_fused(args):
     hist = []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    out5 = torch.empty(5, dtype=torch.float64, device=dev)
     step_ms, gap_ms = [], []
     t0 = time.perf_counter()
     g = float("inf")
@@ -449,23 +485,52 @@ def bench_fused(args):
         e0.record(stream)
         S.srot_step(sol.h, n)
         e1.record(stream)
-        g, f, D = S.srot_gap(sol.h)
+        S.srot_gap_async(sol.h, out5)
+        e2.record(stream)
+        e2.synchronize()
+        g = float(out5[0].item())
         step_ms.append(e0.elapsed_time(e1))
+        gap_ms.append(e1.elapsed_time(e2))
         passes += 1
         hist.append((passes, g))
         if g <= 1e-5:
             break
     wall = time.perf_counter() - t0
+    kind = S.srot_chain_stats(sol.h)[2]
     sol.close()
-    us_step = 1000.0 * float(np.median(step_ms)) / n
-    # per block step: n cost evaluations (3 sub, 3 FMA-class ops) plus the
-    # gradient entry and compare, about 10 FP64 flops each
-    flops_step = 10.0 * n
+    launch_ms = float(np.median(step_ms))
+    sweep_ms = float(np.median(gap_ms))
+    # one launch = n block steps; per step n cost evaluations of 10 FP64
+    # flops (three differences, a product and two FMAs for the squared
+    # distance, an FMA for + w r_j); the sweep evaluates all m n entries once
+    chain_flops = 10.0 * n * n
+    sweep_flops = 10.0 * n * n
+    cc = profile_counters(FUSED_PROFILE, FUSED_SRC, "srot::chain_team_kernel<2, false>")
+    cs = profile_counters(FUSED_PROFILE, FUSED_SRC, "srot::gap_sweep_kernel<2, 1, 2>")
+
+    def valu_share(c):
+        if not c or not c.get("SQ_WAVE_CYCLES"):
+            return None
+        return c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"]
+
+    chain_ach = chain_flops / (launch_ms * 1e-3) / 1e9
+    sweep_ach = sweep_flops / (sweep_ms * 1e-3) / 1e9
+    roofline = dict(kernel="chain_team_kernel<sqeuclid>", bound="valu", achieved=chain_ach,
+                    peak=FP64_PEAK_GFLOPS, unit="GFLOP/s (FP64)", frac=chain_ach / FP64_PEAK_GFLOPS,
+                    flops_per_launch=chain_flops, launch_ms=launch_ms,
+                    counted_flops_per_launch=fp64_counted_flops(cc),
+                    valu_active_share_of_wave_cycles=valu_share(cc),
+                    note="latency-bound: one record exchange between the team's workgroups per block step")
+    sweep = dict(kernel="gap_sweep_kernel<sqeuclid>", bound="valu", achieved=sweep_ach,
+                 peak=FP64_PEAK_GFLOPS, unit="GFLOP/s (FP64)", frac=sweep_ach / FP64_PEAK_GFLOPS,
+                 flops_per_launch=sweep_flops, launch_ms=sweep_ms,
+                 counted_flops_per_launch=fp64_counted_flops(cs),
+                 valu_active_share_of_wave_cycles=valu_share(cs))
     return {"workload": f"m=n={n} mixture points, fused squared-Euclidean cost, b~Dirichlet(1), w=1, "
                         f"to gap 1e-5 (cap {args.fused_seconds:.0f} s)",
-            "passes": passes, "gap": g, "converged": bool(g <= 1e-5), "seconds": wall,
-            "us_per_block_update": us_step, "block_updates_per_s": 1e6 / us_step,
-            "fp64_GFLOPs_chain": flops_step / us_step / 1e3,
+            "chain_kind": kind, "passes": passes, "gap": g, "converged": bool(g <= 1e-5), "seconds": wall,
+            "us_per_block_update": 1000.0 * launch_ms / n, "block_updates_per_s": n / (launch_ms * 1e-3),
+            "roofline": roofline, "gap_sweep": sweep,
             "gap_history": hist[:: max(1, len(hist) // 10)]}
 
 
