@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--weights", type=str, default="0.1,1,10")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solves")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--sections", type=str, default="sweep,fw,variants,batched,diff,fused",
                     help="extra workloads after the stored-cost one: sweep, fw, variants, batched, diff, fused")
     ap.add_argument("--sweep-n", type=int, default=16384)
@@ -534,23 +534,52 @@ def bench_fused(args):
             "gap_history": hist[:: max(1, len(hist) // 10)]}
 
 
+def host_cpu():
+    """Logical CPUs and model name of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(d, m, w, seconds):
-    """FP64 oracle, single thread, on the same workload: whole passes (m block
-    steps + gap) until about `seconds` of CPU time, extrapolated per update."""
+    """The FP64 oracle, single thread, on the same workload and the same
+    block-index stream as the GPU: whole passes (m block steps + gap) until
+    the gap reaches 1e-6 or about `seconds` of CPU time (value = block
+    updates per second over that run), then the small configuration
+    (m = n = 256 uniform points, FP64 cost, w = 1) run in full: 500 passes."""
     from oracle import oracle as O
     from paper_2103_05857_amd import inputs as I
     P = O.Problem(d["a"], d["b"], w, C=d["C"].astype(np.float64))
     st = O.State(P)
     t0 = time.perf_counter()
-    passes = 0
-    while time.perf_counter() - t0 < seconds and passes < 1000:
+    passes, g = 0, float("inf")
+    while time.perf_counter() - t0 < seconds and passes < 2000:
         O.bcfw_steps(P, st, I.philox_uniform_indices(0, passes * m, m, m), trace=False)
-        O.gap(P, st.T)
+        g = O.gap(P, st.T)["g"]
         passes += 1
+        if g <= 1e-6:
+            break
     dt = time.perf_counter() - t0
+    c1 = I.problem_uniform_c1(0, 256, 256)
+    P1 = O.Problem(c1["a"], c1["b"], 1.0, C=c1["C"])
+    s1 = O.State(P1)
+    t1 = time.perf_counter()
+    for p in range(500):
+        O.bcfw_steps(P1, s1, I.philox_uniform_indices(0, p * 256, 256, 256), trace=False)
+    g1 = O.gap(P1, s1.T)["g"]
+    c1_s = time.perf_counter() - t1
     return dict(value=passes * m / dt, unit="block-updates/s", cores=1, kind="oracle",
-                sample=f"{passes} passes (m={m} block steps + gap sweep each) at w={w}, "
-                       f"{dt:.1f} s, single-threaded FP64 C oracle")
+                sample=f"{passes} passes of the {m} x {m} stored-cost workload at w={w} "
+                       f"({'reached gap 1e-6' if g <= 1e-6 else f'stopped at the {seconds:.0f} s cap'}, "
+                       f"gap {g:.3e}), {dt:.1f} s, single-threaded FP64 C oracle, same index stream as the GPU",
+                time_to_gap_1e6_s=(dt if g <= 1e-6 else None), passes=passes,
+                small_config_500_passes_s=c1_s, small_config_gap=g1, host=host_cpu())
 
 
 if __name__ == "__main__":
