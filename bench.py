@@ -283,12 +283,33 @@ def bench_sweep(args):
     # algorithmic bytes: the cost once (4 m n), the plan's support (index +
     # value, 12 B per nonzero), r, b, a and the per-row outputs
     byts = 4.0 * n * n + 12.0 * nnz + 8.0 * (3 * n + 3 * n)
+    # full FW (Alg. A.1) on the same cost: one sweep launch per iteration
+    fw = S.Solver(a, b, C=C, w=1.0, seed=0)
+    S.srot_fw_steps(fw.h, 3)
+    torch.cuda.synchronize()
+    f0 = torch.cuda.Event(enable_timing=True)
+    f1 = torch.cuda.Event(enable_timing=True)
+    iters = 20
+    f0.record(stream)
+    S.srot_fw_steps(fw.h, iters)
+    f1.record(stream)
+    f1.synchronize()
+    fw_s = f0.elapsed_time(f1) * 1e-3 / iters
+    Tf, _ = fw.plan()
+    fw_nnz = int((Tf > 0).sum().item())
+    del Tf
+    fw.close()
+    fw_bytes = 4.0 * n * n + 24.0 * fw_nnz + 8.0 * (3 * n + 4 * n)
     return {"workload": f"gap sweep, m=n={n} FP32 stored cost (1 GiB), after one pass",
             "kernel": "gap_stream_kernel<f32,2,2> (+ 40-byte readback copy)", "bound": "hbm",
             "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS,
             "traffic": counter_traffic("srot::gap_stream_kernel<0, 2, 2>", SWEEP_PROFILE, grid=2048 * 256),
-            "chain_us_per_block_update_first_pass": chain_us}
+            "chain_us_per_block_update_first_pass": chain_us,
+            "full_fw": {"workload": f"full FW, m=n={n}, FP32 stored cost (1 GiB), w=1, ELS, iterations 4-23",
+                        "us_per_iteration": fw_s * 1e6, "bytes_per_iteration": fw_bytes,
+                        "achieved": fw_bytes / fw_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": fw_bytes / fw_s / 1e9 / HBM_PEAK_GBS}}
 
 
 def bench_fw(args, C, a, b):

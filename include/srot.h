@@ -318,15 +318,22 @@ int srot_solve_ga(srot_handle *h, double init, int64_t period, double *out3, int
  * FW iteration counter of the handle, from 0) or the exact line search of
  * eq. AppenEq:SemiRelaxedFWStep, gamma = clip(<T - S, grad f> /
  * (w ||(T - S)^T 1||^2), 0, 1), as opt->step_rule says.  Shares the plan,
- * residual and masks with the block-coordinate entry points.
+ * residual and masks with the block-coordinate entry points.  Each
+ * iteration is one launch of the gap sweep, which applies the previous
+ * iteration's step to each row as it reaches it and sums the vertex columns
+ * in fixed point (order-independent: runs are reproducible); a last
+ * launch applies the final step, so the plan is complete when the call's
+ * work has run.
  *   iters        number of iterations (enqueued; no synchronisation).
  *   trace_gamma  device, iters doubles (optional): the step sizes. */
 int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma);
 
 /* Full Frank-Wolfe until the gap measured at an iterate is <= opt->eps or
  * opt->max_passes iterations have run.  out3 (host) = {g, f, D} at the last
- * iterate; *iters (host) = iterations run.  Synchronises every iteration.
- * Returns SROT_OK or SROT_NOT_CONVERGED. */
+ * iterate; *iters (host) = iterations run.  The stop test runs on the
+ * device (a sweep that finds the run converged does nothing), so
+ * iterations are queued in batches of 8 and the host synchronises once per
+ * batch.  Returns SROT_OK or SROT_NOT_CONVERGED. */
 int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters);
 
 /* Barycentric projection of the source points through the plan

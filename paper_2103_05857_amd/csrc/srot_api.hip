@@ -130,7 +130,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.j = off; off = align_up(off + sizeof(int32_t) * (size_t)m);
     L.g = off; off = align_up(off + sizeof(double) * (size_t)m);
     L.partials = off;
-    off = align_up(off + sizeof(double) * std::max<size_t>(8 * (size_t)L.gap_blocks, (size_t)srot::fw_finish_blocks(n)));
+    off = align_up(off + sizeof(double) * 8 * (size_t)L.gap_blocks);
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.slow = off; off = align_up(off + 4 * sizeof(int64_t));
@@ -539,27 +539,51 @@ int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma)
 {
     if (!h) return fail(SROT_EINVAL, "srot_fw_steps: NULL handle");
     if (iters < 0) return fail(SROT_EINVAL, "srot_fw_steps: iters < 0");
+    if (iters == 0) return SROT_OK;
+    SROT_HIP(srot::launch_fw_reset(h->P, h->S, h->stream));
     for (int64_t it = 0; it < iters; ++it) {
-        SROT_HIP(srot::launch_fw_step(h->P, h->S, h->fw_k, h->opt.step_rule,
-                                      trace_gamma ? trace_gamma + it : nullptr, h->stream));
-        h->fw_k += 1;
+        const srot::FwSweep f = srot::fw_sweep_args(h->S, -1.0, h->opt.step_rule, 1, h->fw_k + it,
+                                                    trace_gamma ? trace_gamma + it : nullptr);
+        SROT_HIP(srot::launch_fw_iteration(h->P, h->S, f, h->stream));
     }
+    SROT_HIP(srot::launch_fw_flush(h->P, h->S, h->stream));
+    h->fw_k += iters;
     return SROT_OK;
 }
+
+// Iterations are queued in batches; each sweep checks the device's done
+// flag, so the host reads the state once per batch.
+constexpr int64_t kFwBatch = 8;
 
 int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters)
 {
     if (!h || !out3 || !iters) return fail(SROT_EINVAL, "srot_fw_solve: NULL argument");
     *iters = 0;
-    for (int64_t it = 0;; ++it) {
-        int rc = measure_gap(h, out3);  // the sweep also gives every row's vertex
-        if (rc != SROT_OK) return rc;
-        if (out3[0] <= h->opt.eps) return SROT_OK;
-        if (it >= h->opt.max_passes) return SROT_NOT_CONVERGED;
-        SROT_HIP(srot::launch_fw_update(h->P, h->S, h->fw_k, h->opt.step_rule, nullptr, h->stream));
-        h->fw_k += 1;
-        *iters = it + 1;
+    const int64_t maxit = h->opt.max_passes;
+    SROT_HIP(srot::launch_fw_reset(h->P, h->S, h->stream));
+    int64_t launched = 0;
+    int32_t state[3] = {0, 0, 0};
+    double sc[3] = {0.0, 0.0, 0.0};
+    for (;;) {
+        // sweeps launched + q for q < batch: the one numbered maxit only measures
+        const int64_t batch = std::min<int64_t>(kFwBatch, maxit + 1 - launched);
+        for (int64_t q = 0; q < batch; ++q) {
+            const int64_t it = launched + q;
+            const srot::FwSweep f = srot::fw_sweep_args(h->S, h->opt.eps, h->opt.step_rule, it < maxit ? 1 : 0,
+                                                        h->fw_k + it, nullptr);
+            SROT_HIP(srot::launch_fw_iteration(h->P, h->S, f, h->stream));
+        }
+        launched += batch;
+        SROT_HIP(hipMemcpyAsync(state, h->S.flags + 1, sizeof(state), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipMemcpyAsync(sc, h->S.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipStreamSynchronize(h->stream));
+        if (state[0] || launched > maxit) break;
     }
+    SROT_HIP(srot::launch_fw_flush(h->P, h->S, h->stream));
+    *iters = state[2];
+    h->fw_k += state[2];
+    out3[0] = sc[0]; out3[1] = sc[1]; out3[2] = sc[2];
+    return state[0] ? SROT_OK : SROT_NOT_CONVERGED;
 }
 
 int srot_step_variant(srot_handle *h, int variant, int64_t nsteps, const int32_t *idx, int32_t *trace_j,

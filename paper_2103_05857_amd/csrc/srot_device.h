@@ -262,6 +262,52 @@ __device__ __forceinline__ void load_cost_row(const CT *__restrict__ row, int n,
     }
 }
 
+// Full FW's step on one row (Alg. A.1): t_ij <- (1 - gamma) t_ij +
+// gamma a_i [j == js] on the row's support and at its vertex js, with the
+// support masks kept; lanes lane0, lane0 + nl, ... of the caller take the
+// row's mask slots.  Used lazily by the sweep that follows the step and by
+// the flush at the end of a run.
+__device__ __forceinline__ void fw_apply_row(int i, int n, double gamma, double ai, int js, const Ownership &own,
+                                             double *__restrict__ T, uint32_t *__restrict__ M, int lane0, int nl)
+{
+    const int slots = own.words * own.nt;
+    const size_t base = (size_t)i * (size_t)n;
+    const double gadd = gamma * ai;
+    const int jg = js / own.vec;
+    const int ts_star = jg % own.nt;
+    const int u_star = (jg / own.nt) * own.vec + (js % own.vec);
+    constexpr int AW = 8;  // mask words requested at once per lane
+    for (int s0 = lane0; s0 < slots; s0 += nl * AW) {
+        uint32_t mkv[AW];
+#pragma unroll
+        for (int q = 0; q < AW; ++q) {
+            const int s = s0 + q * nl;
+            mkv[q] = (s < slots) ? M[(size_t)i * slots + s] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < AW; ++q) {
+            const int s = s0 + q * nl;
+            if (s >= slots) break;
+            const int wd = s / own.nt, ts = s - wd * own.nt;
+            const uint32_t mk = mkv[q];
+            uint32_t todo = mk, nm = mk;
+            if (ts == ts_star && (u_star >> 5) == wd) todo |= 1u << (u_star & 31);
+            while (todo) {
+                const int bt = __ffs(todo) - 1;
+                todo &= todo - 1u;
+                const int u = wd * 32 + bt;
+                const int j = ((u / own.vec) * own.nt + ts) * own.vec + (u % own.vec);
+                const bool on = (mk >> bt) & 1u;
+                const double t = on ? T[base + j] : 0.0;
+                const double tn = (1.0 - gamma) * t + ((j == js) ? gadd : 0.0);
+                if (tn != t || !on) T[base + j] = tn;
+                nm = (tn != 0.0) ? (nm | (1u << bt)) : (nm & ~(1u << bt));
+            }
+            if (nm != mk) M[(size_t)i * slots + s] = nm;
+        }
+    }
+}
+
 // (1 - gamma) t + gamma * add: the block update of Alg. 1 for one entry, one
 // expression shared by every code path so that all paths round alike.
 __device__ __forceinline__ double blend(double t, double gamma, double add)

@@ -135,17 +135,52 @@ int32_t adjoint_slices_cap(int64_t m);
 // doubles of per-slice dY column sums (adj_part) that launch_adjoint uses
 size_t adjoint_part_doubles(const ProblemView &P, const Ownership &own);
 
-// Full Frank-Wolfe iteration (srot_fw.hip): launch_fw_update runs the vertex
-// column sums, the step size (scalars[5]) and the update after a gap sweep;
-// launch_fw_step is the sweep followed by the update.  trace_gamma (device,
-// optional) receives this iteration's step size.  k: FW iteration counter.
-hipError_t launch_fw_update(const ProblemView &P, const DeviceState &S, int64_t k, int rule,
-                            double *trace_gamma, hipStream_t stream);
-hipError_t launch_fw_step(const ProblemView &P, const DeviceState &S, int64_t k, int rule,
-                          double *trace_gamma, hipStream_t stream);
-// Workgroups of the FW step-size reduction (the gap partial buffer holds
-// at least this many doubles).
-int32_t fw_finish_blocks(int64_t n);
+// Full Frank-Wolfe (Alg. A.1) as two launches per iteration.  The sweep of
+// iteration k first applies the step of iteration k - 1 to each row as it
+// reaches it (t_i <- (1 - gamma) t_i + gamma a_i e_{j*_i}, gamma in
+// scalars[5], j*_i in row_j), then measures the row's vertex and gap at the
+// new plan and adds a_i to the vertex column sum s = S^T 1 (fixed point,
+// device-scope integer atomics: order-free, so the sums are reproducible).
+// The step kernel (srot_fw.hip) then either stops (gap <= eps, or a
+// measuring-only sweep) or takes the line search on d = r + b - s, writes
+// gamma and the new residual r <- (1 - gamma)(r + b) + gamma s - b, and
+// leaves the row updates pending for the next sweep.  Launches that find
+// the done flag set return at once, so the host can queue iterations and
+// read the flag once per batch.
+struct FwSweep {
+    int32_t *state;                 // [0] done, [1] a step is pending, [2] steps taken
+    unsigned long long *s_fixed;    // n vertex column sums, zero between sweeps
+    const double *scale;            // fixed-point scale of a (device, one double)
+    double eps;                     // stop once the measured gap is <= eps (negative: never)
+    int32_t rule;                   // SROT_ELS / SROT_DEC
+    int32_t allow_step;             // 0: measure only
+    int64_t k;                      // FW iteration counter (decay rule 2/(k+2))
+    double *trace_gamma;            // device, one entry, or null
+};
+hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream);
+// One FW iteration: the FW sweep and the step kernel.
+hipError_t launch_fw_iteration(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream);
+// Before a run of FW sweeps: done / pending / steps cleared, s zeroed, the
+// fixed-point scale of a computed (srot_fw.hip).
+hipError_t launch_fw_reset(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+// After a run: applies a pending step to every row (srot_fw.hip).
+hipError_t launch_fw_flush(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+// Device words of the FW run state inside DeviceState (flags[1..3]) and the
+// scale (scalars[7]); s lives in adj_part.
+inline FwSweep fw_sweep_args(const DeviceState &S, double eps, int rule, int allow_step, int64_t k,
+                             double *trace_gamma)
+{
+    FwSweep f;
+    f.state = S.flags + 1;
+    f.s_fixed = reinterpret_cast<unsigned long long *>(S.adj_part);
+    f.scale = S.scalars + 7;
+    f.eps = eps;
+    f.rule = rule;
+    f.allow_step = allow_step;
+    f.k = k;
+    f.trace_gamma = trace_gamma;
+    return f;
+}
 
 // Block steps with away (pairwise = 0, Alg. A.2) or pairwise (pairwise = 1,
 // Alg. A.3) directions (srot_variants.hip); rows of at most 4096 columns.

@@ -633,16 +633,16 @@ __device__ __forceinline__ void gap_finish(const ProblemView &P, const double *_
     }
 }
 
-template <int COST, int VEC, int R>
-__global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const double *__restrict__ T,
-                                                           const double *__restrict__ rg,
-                                                           const uint32_t *__restrict__ M, Ownership own,
+template <int COST, int VEC, int R, bool FW>
+__global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double *__restrict__ T,
+                                                           double *__restrict__ rg,
+                                                           uint32_t *__restrict__ M, Ownership own,
                                                            double *__restrict__ row_G,
                                                            int32_t *__restrict__ row_j,
                                                            double *__restrict__ row_g,
                                                            double *__restrict__ partials,
                                                            int32_t *__restrict__ ticket,
-                                                           double *__restrict__ out)
+                                                           double *__restrict__ out, FwSweep fw)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
@@ -654,9 +654,25 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const 
     const int slots = own.words * own.nt;
     const int nq = (n + 64 * VEC - 1) / (64 * VEC);
 
+    bool pending = false;
+    double gprev = 0.0, scale = 0.0;
+    if constexpr (FW) {
+        if (fw.state[0]) return;  // the run has reached its gap: every workgroup leaves
+        pending = fw.state[1] != 0;
+        gprev = out[5];
+        scale = *fw.scale;
+    }
     double aG = 0.0, lin = 0.0, gs = 0.0;
     const int stride = gridDim.x * GAP_NW * R;
     for (int i0 = (blockIdx.x * GAP_NW + wid) * R; i0 < m; i0 += stride) {
+        if constexpr (FW) {
+            // the previous iteration's step on these rows (their old vertices)
+            if (pending) {
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (i0 + k < m) fw_apply_row(i0 + k, n, gprev, P.a[i0 + k], row_j[i0 + k], own, T, M, lane, 64);
+            }
+        }
         int ir[R];
         float xr[R][3];
 #pragma unroll
@@ -810,6 +826,11 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, const 
                 row_G[i] = G;
                 row_j[i] = J;
                 row_g[i] = x[0];
+                // full FW: a_i joins its vertex column's sum (the atomics
+                // have completed when the kernel ends)
+                if constexpr (FW)
+                    __hip_atomic_fetch_add(fw.s_fixed + J, (unsigned long long)__double2ull_rn(P.a[i] * scale),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             aG += P.a[i] * G;
             lin += x[1];
@@ -833,16 +854,16 @@ constexpr int GAP_MW = 8;  // mask words per lane and row read ahead
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int COST, int R, int GU>
-__global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, const double *__restrict__ T,
-                                                            const double *__restrict__ rg,
-                                                            const uint32_t *__restrict__ M, Ownership own,
+template <int COST, int R, int GU, bool FW>
+__global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, double *__restrict__ T,
+                                                            double *__restrict__ rg,
+                                                            uint32_t *__restrict__ M, Ownership own,
                                                             double *__restrict__ row_G,
                                                             int32_t *__restrict__ row_j,
                                                             double *__restrict__ row_g,
                                                             double *__restrict__ partials,
                                                             int32_t *__restrict__ ticket,
-                                                            double *__restrict__ out)
+                                                            double *__restrict__ out, FwSweep fw)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr int VEC = 16 / (int)sizeof(CT);  // columns per 16-byte vector
@@ -855,6 +876,14 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, const
     const int nq = (n + 64 * VEC - 1) / (64 * VEC);
     const __amdgpu_buffer_rsrc_t rs_r = buf_rsrc(rg, (unsigned)n * 8u);
 
+    bool pending = false;
+    double gprev = 0.0, scale = 0.0;
+    if constexpr (FW) {
+        if (fw.state[0]) return;  // the run has reached its gap: every workgroup leaves
+        pending = fw.state[1] != 0;
+        gprev = out[5];
+        scale = *fw.scale;
+    }
     double aG = 0.0, lin = 0.0, gs = 0.0;
     const int stride = gridDim.x * GAP_NW * R;
     for (int i0 = (blockIdx.x * GAP_NW + wid) * R; i0 < m; i0 += stride) {
@@ -865,12 +894,6 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, const
         for (int k = 0; k < R; ++k) {
             ir[k] = (i0 + k < m) ? i0 + k : m - 1;
             rs_c[k] = buf_rsrc(C + (size_t)ir[k] * (size_t)n, (unsigned)(n * sizeof(CT)));
-            // rows past the end read an empty range: no support, no cost
-            const __amdgpu_buffer_rsrc_t rs_m =
-                buf_rsrc(M + (size_t)ir[k] * slots, (i0 + k < m) ? (unsigned)slots * 4u : 0u);
-#pragma unroll
-            for (int q = 0; q < GAP_MW; ++q)
-                mw[k][q] = __builtin_amdgcn_raw_buffer_load_b32(rs_m, (int)((lane + 64 * q) * 4), 0, 0);
         }
         u32x4 ca[R][GU], cb[R][GU];
         u32x4 ra[GU][RV], rb[GU][RV];
@@ -920,6 +943,25 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, const
             }
         };
         issue(ca, ra, 0);
+        if constexpr (FW) {
+            // the previous iteration's step on these rows (their old
+            // vertices), while the first cost batch is on its way
+            if (pending) {
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (i0 + k < m) fw_apply_row(i0 + k, n, gprev, P.a[i0 + k], row_j[i0 + k], own, T, M, lane, 64);
+                drain_memory();
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            // rows past the end read an empty range: no support, no cost
+            const __amdgpu_buffer_rsrc_t rs_m =
+                buf_rsrc(M + (size_t)ir[k] * slots, (i0 + k < m) ? (unsigned)slots * 4u : 0u);
+#pragma unroll
+            for (int q = 0; q < GAP_MW; ++q)
+                mw[k][q] = __builtin_amdgcn_raw_buffer_load_b32(rs_m, (int)((lane + 64 * q) * 4), 0, 0);
+        }
 
         // support entries of the rows from the mask words (first GAP_KS per
         // lane and row gathered now, further ones after the scan)
@@ -1008,6 +1050,11 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, const
                 row_G[i] = G;
                 row_j[i] = J;
                 row_g[i] = x[0];
+                // full FW: a_i joins its vertex column's sum (the atomics
+                // have completed when the kernel ends)
+                if constexpr (FW)
+                    __hip_atomic_fetch_add(fw.s_fixed + J, (unsigned long long)__double2ull_rn(P.a[i] * scale),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             aG += P.a[i] * G;
             lin += x[1];
@@ -1376,45 +1423,63 @@ int32_t gap_blocks_for(int64_t m)
 // Row-strided sweep (fused cost, or rows not split into 16-byte vectors):
 // at most 1024 workgroups, where it measured best.
 template <int COST, int VEC>
-static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, hipStream_t st)
+static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st)
 {
     constexpr int R = 2;  // each r_j read serves both rows
     const int64_t waves = (P.m + R - 1) / R;
     const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, 1024), S.gap_blocks);
-    hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
-                       S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars);
+    if (fw)
+        hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R, true>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
+                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, *fw);
+    else
+        hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R, false>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
+                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, FwSweep{});
     return hipGetLastError();
 }
 
 // Stored cost in 16-byte vectors: two rows per wave, double-buffered
 // batches of two vectors (FP32) or four (FP64) per lane and row.
 template <int COST>
-static hipError_t launch_gap_stream(const ProblemView &P, const DeviceState &S, hipStream_t st)
+static hipError_t launch_gap_stream(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st)
 {
     constexpr int R = 2, GU = (COST == SROT_COST_F32) ? 2 : 4;
     const int64_t waves = (P.m + R - 1) / R;
     const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, GAP_MAX_BLOCKS),
                                           S.gap_blocks);
-    hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
-                       S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars);
+    if (fw)
+        hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU, true>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
+                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, *fw);
+    else
+        hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU, false>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
+                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, FwSweep{});
     return hipGetLastError();
 }
 
-hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream)
+static hipError_t launch_gap_any(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t stream)
 {
     const uintptr_t cbase = (uintptr_t)P.C;
     // buffer ranges of one cost row and of r are 32-bit byte counts
     const bool ranged = (int64_t)P.n * 8 < (int64_t)0x7fffffff;
     switch (P.cost) {
     case SROT_COST_F32:
-        if (P.n % 4 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F32>(P, S, stream);
-        return launch_gap_rows<SROT_COST_F32, 1>(P, S, stream);
+        if (P.n % 4 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F32>(P, S, fw, stream);
+        return launch_gap_rows<SROT_COST_F32, 1>(P, S, fw, stream);
     case SROT_COST_F64:
-        if (P.n % 2 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F64>(P, S, stream);
-        return launch_gap_rows<SROT_COST_F64, 1>(P, S, stream);
+        if (P.n % 2 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F64>(P, S, fw, stream);
+        return launch_gap_rows<SROT_COST_F64, 1>(P, S, fw, stream);
     default:
-        return launch_gap_rows<SROT_COST_SQEUCLID, 1>(P, S, stream);
+        return launch_gap_rows<SROT_COST_SQEUCLID, 1>(P, S, fw, stream);
     }
+}
+
+hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream)
+{
+    return launch_gap_any(P, S, nullptr, stream);
+}
+
+hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream)
+{
+    return launch_gap_any(P, S, &fw, stream);
 }
 
 }  // namespace srot

@@ -142,3 +142,58 @@ def test_barycentric_projection_matches_oracle(cost_mode, m, n):
     ref = O.barycentric(T.cpu().numpy(), d["X"], d["Y"])
     np.testing.assert_allclose(Xh.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
     sol.close()
+
+
+@pytest.mark.parametrize("cost_mode,dtype,m,n,w,eps", [
+    ("stored", np.float64, 64, 96, 1.0, 1e-4),
+    ("stored", np.float32, 200, 512, 0.5, 1e-5),      # 16-byte stream sweep
+    ("sqeuclid", None, 37, 6001, 2.0, 1e-4),          # wide fused rows
+])
+def test_fw_solve_stops_where_the_oracle_does(cost_mode, dtype, m, n, w, eps):
+    """The stop test of Alg. A.1 runs on the device (iterations queued in
+    batches of 8): the run stops at the first iterate whose gap is <= eps,
+    the same iterate as the oracle's, with the same plan, f and g."""
+    S = _S()
+    d = I.problem_mixture(10, m, n, cost_dtype=dtype or np.float32)
+    P = _oracle(d, cost_mode, w)
+    T = O.init_plan(P)
+    k = 0
+    while True:
+        gk = O.gap(P, T)["g"]
+        if gk <= eps or k > 5000:
+            break
+        O.fw_iteration(P, T, k, rule=O.ELS)
+        k += 1
+    ref = O.gap(P, T)
+    # no iterate's gap lies near eps (a near tie would make the stop iterate
+    # depend on rounding)
+    sol = _solver(d, cost_mode, w, eps=eps, max_passes=20000)
+    st, (g, f, D), iters = S.srot_fw_solve(sol.h)
+    assert st == S.SROT_OK and iters == k, (iters, k)
+    Tg, r = sol.plan()
+    np.testing.assert_allclose(Tg.cpu().numpy(), T, rtol=0, atol=1e-9)
+    assert abs(f - ref["f"]) <= 1e-6 * abs(ref["f"]) + 1e-15
+    assert abs(g - ref["g"]) <= 1e-6 * max(ref["g"], 1e-9) + 1e-15
+    sol.close()
+
+
+@pytest.mark.parametrize("maxit", [5, 8, 13])
+def test_fw_solve_stops_after_max_iterations(maxit):
+    """With an unreachable gap the run takes max_passes iterations, measures
+    the gap once more and reports SROT_NOT_CONVERGED; its plan is bit for bit
+    the plan of the same number of srot_fw_steps iterations."""
+    S = _S()
+    m, n, w = 70, 130, 1.0
+    d = I.problem_mixture(11, m, n, cost_dtype=np.float64)
+    a = _solver(d, "stored", w, eps=0.0, max_passes=maxit)
+    st, (g, f, D), iters = S.srot_fw_solve(a.h)
+    assert st == S.SROT_NOT_CONVERGED and iters == maxit
+    b = _solver(d, "stored", w)
+    S.srot_fw_steps(b.h, maxit)
+    ga, _, _ = a.gap()
+    Ta, ra = a.plan()
+    Tb, rb = b.plan()
+    assert torch.equal(Ta, Tb) and torch.equal(ra, rb)
+    assert g == ga
+    a.close()
+    b.close()
