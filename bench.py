@@ -401,15 +401,42 @@ def bench_batched(args):
     bs = S.BatchSolver(Cs, As, Bs, tune=True, **opts)
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t0
-    bs.solve()                                   # warm-up replay
+    # the first solve starts the largest problems first; later solves start
+    # the previous solve's longest-running problems first
+    t0 = time.perf_counter()
+    bs.solve()
+    first_s = time.perf_counter() - t0
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
         st, out3, passes, status = bs.solve()
         times.append(time.perf_counter() - t0)
-    tiles, _ = bs.tiles()
+    tiles, tune_ms = bs.tiles()
     bs.close()
+    # the same batch initialised again: tiles from the tuning cache
+    t0 = time.perf_counter()
+    bs2 = S.BatchSolver(Cs, As, Bs, tune=True, **opts)
+    torch.cuda.synchronize()
+    init_warm_s = time.perf_counter() - t0
+    tiles2, _ = bs2.tiles()
+    bs2.close()
     solve_s = float(np.median(times))
+    # the straggler (most block steps) and its floor: the same problem alone
+    # on the single-problem solver, which picks its fastest chain
+    sp = int(np.argmax(passes * ms))
+    sol = S.Solver(As[sp], Bs[sp], C=Cs[sp], **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, sp_passes = sol.solve()
+    floor_s = time.perf_counter() - t0
+    sp_kind = S.srot_chain_stats(sol.h)[2]
+    sol.close()
+    straggler = {"problem": sp, "m": int(ms[sp]), "n": int(ns[sp]), "passes": int(passes[sp]),
+                 "batch_tile": "x".join(str(int(v)) for v in tiles[sp]),
+                 "batch_us_per_block_update": 1e3 * float(tune_ms[sp]) if tune_ms[sp] > 0 else None,
+                 "alone_seconds": floor_s, "alone_passes": int(sp_passes), "alone_chain_kind": int(sp_kind),
+                 "alone_us_per_block_update": 1e6 * floor_s / (sp_passes * int(ms[sp])),
+                 "batch_wall_over_floor": solve_s / floor_s}
     updates = int((passes * ms).sum())
     # cost bytes streamed: a row of 4n bytes per block step, 4mn per gap sweep
     cbytes = float((passes * ms * 4 * ns).sum() + (passes * 4 * ms * ns).sum())
@@ -427,11 +454,12 @@ def bench_batched(args):
     uniq, cnt = np.unique(tiles, axis=0, return_counts=True)
     return {
         "workload": f"{count} problems, m,n log-uniform in [64,4096], FP32 stored cost, w=1, gap<=1e-6",
-        "converged": int((status == 0).sum()), "seconds": solve_s,
+        "converged": int((status == 0).sum()), "seconds": solve_s, "first_solve_seconds": first_s,
         "block_updates": updates, "block_updates_per_s": updates / solve_s,
         "c_stream_GBps": cbytes / solve_s / 1e9, "c_stream_frac_hbm": cbytes / solve_s / 1e9 / HBM_PEAK_GBS,
         "passes_mean": float(passes.mean()), "passes_max": int(passes.max()),
-        "init_and_autotune_s": init_s,
+        "init_and_autotune_s": init_s, "init_cached_tiles_s": init_warm_s,
+        "cached_tiles_match": bool(np.array_equal(tiles, tiles2)), "straggler": straggler,
         "tiles": {f"{a}x{b}x{c}": int(n_) for (a, b, c), n_ in zip(uniq.tolist(), cnt.tolist())},
         "sequential": {"sample_problems": k, "seconds": seq_s, "block_updates_per_s": seq_rate,
                        "extrapolated_seconds_all": updates / seq_rate},

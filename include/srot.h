@@ -370,8 +370,12 @@ size_t srot_workspace_size_batched(int32_t count, const int64_t *m, const int64_
  *   opt      host; cost must be SROT_COST_F32, sampling SROT_UNIFORM.
  *   tune     0: each problem gets the tile shape srot_init would choose;
  *            1: per group of problems sharing that shape, every compiled
- *            candidate shape is timed on the group's largest problem (two
- *            passes) and the fastest is kept.
+ *            candidate shape is timed on the group's largest problem (one
+ *            pass, second of two runs) and the fastest is kept.  Choices
+ *            are cached per size class (default shape, widest row,
+ *            16-byte rows) for the process, and in the file of JSON lines
+ *            named by the environment variable SROT_TUNE_CACHE, if set
+ *            (read once, appended to); a cached class is not timed again.
  *   stream   hipStream_t for all work of the batch.
  * Validates the inputs on the device, builds and instantiates the graph,
  * and synchronises.  Errors: SROT_EINVAL, SROT_ENOMEM, SROT_ENONFINITE,
@@ -381,11 +385,14 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
                       void *workspace, size_t ws_bytes, const srot_options *opt, int32_t tune,
                       void *stream);
 
-/* Solves every problem from its initial plan (one graph launch) and
+/* Solves every problem from its initial plan (one graph launch: at most
+ * four concurrent kernel launches, one per launch class of tile shapes) and
  * synchronises.  Host outputs, each optional: out3 (count x 3: g, f, D at
  * the last gap sweep), passes (count), status (count: SROT_OK or
  * SROT_NOT_CONVERGED).  Returns SROT_OK when every problem converged,
- * SROT_NOT_CONVERGED otherwise. */
+ * SROT_NOT_CONVERGED otherwise.  Each call also reorders the problems'
+ * start order for the next call (longest measured run time first); a
+ * problem's results do not depend on that order. */
 int srot_solve_batched(srot_batch *h, double *out3, int64_t *passes, int32_t *status);
 
 /* Copies problem p's plan (device, m x n double, zeros off the support) and

@@ -9,13 +9,21 @@
 // problem solved here follows the same trajectory as srot_solve with the
 // same tile shape and seed.
 //
-// Problems are grouped by tile shape (threads x columns per thread x vector
-// width); each group is one launch of batch_solve_kernel, one workgroup per
-// problem, largest problems first.  The group launches are independent
-// nodes of one hipGraph, instantiated once and replayed by every
-// srot_solve_batched call.  The tile shape of each group is either the
-// single-problem default or the fastest candidate measured on the group's
-// largest problem (srot_init_batched with tune = 1).
+// Each problem has a tile shape (threads x columns per thread x vector
+// width): either the single-problem default for its width or, with
+// srot_init_batched(tune = 1), the fastest candidate measured on the largest
+// problem of its default shape.  Shapes of one workgroup size (and, at 256
+// threads, one vector width) form a launch class: one launch of
+// batch_solve_kernel per class, one workgroup per problem, which switches
+// to the problem's shape.  The (at most four) class launches are
+// independent nodes of one hipGraph, instantiated once and replayed by
+// every srot_solve_batched call; four launches fit the four hardware queues
+// a process gets by default, so they all run at once (launches that share
+// a queue would run one after another).  Within a class the workgroups
+// start in launch order: the largest problems first, and from the second
+// solve on the longest-running ones of the previous solve (per-problem
+// run times come from the device clock), so that the slowest problem of a
+// batch starts at once instead of behind the short ones.
 //
 // Workspace (caller-owned): problem table, launch order, results, then per
 // problem r (n), block indices (m), support masks (m x 256 words) and the
@@ -24,9 +32,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "../../include/srot.h"
@@ -44,12 +56,15 @@ struct BatchProblem {
     int64_t r_off;    // doubles of the residual arena
     int64_t M_off;    // words of the mask arena
     int64_t idx_off;  // entries of the index arena
+    int32_t tile;     // tile id (the instantiation that solves it)
+    int32_t pad;
 };
 
 struct BatchResult {
     double g, f, D;
     int64_t passes;
     int32_t status, pad;
+    int64_t ticks;  // the workgroup's run time, in ticks of the constant-rate device clock
 };
 
 struct BatchParams {
@@ -64,68 +79,167 @@ namespace {
 constexpr int kMaskNT = 256;  // mask words reserved per row (the widest tile used here)
 
 // Duality-gap sweep of one problem by one workgroup (Thm 2, eq. AppenEq:Gi,
-// dual of App. D).  Wave `wid` takes rows wid, wid + NW, ...; per row the
-// wave streams the cost row (lowest-index argmin of c_ij + w r_j), then sums
-// t_ij (v_ij - G_i) and t_ij c_ij over the support.  The waves' row sums are
-// added in wave order; the result is the same in every thread.
-template <int NT, int VEC>
+// dual of App. D).  Wave `wid` takes rows in groups of BG_R: rows
+// wid * BG_R + k, then NW * BG_R further on, ...  For a group the wave
+// requests the rows' support-mask words first, then streams the cost rows
+// in batches of U columns per lane (all R rows at once, each r_j read once
+// for the R rows), so a batch is one round of memory latency; the support
+// entries (the first BG_KS per lane and row, found from the mask words) are
+// requested before the first batch is consumed.  Per row: the lowest-index
+// argmin of c_ij + w r_j, then t_ij (v_ij - G_i) and t_ij c_ij summed over
+// the support.  A wave adds its rows in row order, the waves are added in
+// wave order; the result is the same in every thread.
+constexpr int BG_R = 4;   // rows per wave and group
+constexpr int BG_KS = 2;  // support entries per lane and row gathered ahead
+
+template <int NT, int CPT, int VEC>
 __device__ void batch_gap(const ProblemView &P, const double *__restrict__ T,
                           const double *__restrict__ rg, const uint32_t *__restrict__ M,
                           double &g_out, double &f_out, double &D_out)
 {
     constexpr int NW = NT / 64;
+    constexpr int WPL = NT / 64;  // mask words per lane and row
+    // vectors of VEC columns per lane and batch: up to 16 columns
+    constexpr int PER_LANE = (NT * CPT) / (64 * VEC);
+    constexpr int U = PER_LANE < 16 / VEC ? (PER_LANE > 0 ? PER_LANE : 1) : 16 / VEC;
+    using CV = typename std::conditional<VEC == 4, float4, float>::type;
     __shared__ double s_w[NW][3];
     __shared__ double s_rb[NW][2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int m = P.m, n = P.n;
+    const int nv = n / VEC;  // whole vectors (VEC = 4 only with n % 4 == 0)
     const double w = P.w;
     const float *__restrict__ C = (const float *)P.C;
     double aG = 0.0, lin = 0.0, gs = 0.0;
-    for (int i = wid; i < m; i += NW) {
-        const float *__restrict__ crow = C + (size_t)i * (size_t)n;
-        double best = INFINITY;
-        int bj = 0x7fffffff;
-        if constexpr (VEC == 4) {
-            const float4 *__restrict__ c4 = reinterpret_cast<const float4 *>(crow);
-            const double2 *__restrict__ r2 = reinterpret_cast<const double2 *>(rg);
-            const int ng = n / 4;
-            for (int q = lane; q < ng; q += 64) {
-                const float4 cv = c4[q];
-                const double2 ra = r2[2 * q], rb = r2[2 * q + 1];
-                const double v0 = (double)cv.x + w * ra.x, v1 = (double)cv.y + w * ra.y;
-                const double v2 = (double)cv.z + w * rb.x, v3 = (double)cv.w + w * rb.y;
-                if (v0 < best) { best = v0; bj = 4 * q; }
-                if (v1 < best) { best = v1; bj = 4 * q + 1; }
-                if (v2 < best) { best = v2; bj = 4 * q + 2; }
-                if (v3 < best) { best = v3; bj = 4 * q + 3; }
-            }
-        } else {
-            for (int j = lane; j < n; j += 64) {
-                const double v = (double)crow[j] + w * rg[j];
-                if (v < best) { best = v; bj = j; }
-            }
-        }
-        wave_argmin(best, bj);
-        double x[2] = {0.0, 0.0};
-        for (int ts = lane; ts < NT; ts += 64) {
-            uint32_t mk = M[(size_t)i * NT + ts];
-            while (mk) {
-                const int u = __ffs(mk) - 1;
-                mk &= mk - 1u;
-                const int j = owned_col<NT, VEC>(u, ts);
-                const double t = T[(size_t)i * (size_t)n + j];
-                const double c = (double)crow[j];
-                x[0] += t * (c + w * rg[j] - best);
-                x[1] += t * c;
+    for (int i0 = wid * BG_R; i0 < m; i0 += NW * BG_R) {
+        int ir[BG_R];
+#pragma unroll
+        for (int k = 0; k < BG_R; ++k) ir[k] = i0 + k < m ? i0 + k : m - 1;
+        uint32_t mw[BG_R][WPL];
+#pragma unroll
+        for (int k = 0; k < BG_R; ++k)
+#pragma unroll
+            for (int q = 0; q < WPL; ++q)
+                mw[k][q] = i0 + k < m ? M[(size_t)ir[k] * NT + lane + 64 * q] : 0u;
+        // support entries: the lane's slots in increasing order, bits low to high
+        int sj[BG_R][BG_KS];
+        bool more[BG_R];
+#pragma unroll
+        for (int k = 0; k < BG_R; ++k) {
+            int found = 0;
+            more[k] = false;
+#pragma unroll
+            for (int e = 0; e < BG_KS; ++e) sj[k][e] = -1;
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) {
+                uint32_t mk = mw[k][q];
+                while (mk) {
+                    const int u = __ffs(mk) - 1;
+                    mk &= mk - 1u;
+                    if (found < BG_KS) {
+#pragma unroll
+                        for (int e = 0; e < BG_KS; ++e)
+                            sj[k][e] = e == found ? owned_col<NT, VEC>(u, lane + 64 * q) : sj[k][e];
+                        ++found;
+                    } else {
+                        more[k] = true;
+                    }
+                }
             }
         }
-        wave_sum<2>(x);
-        aG += P.a[i] * best;
-        lin += x[1];
-        gs += x[0];
+        double st[BG_R][BG_KS], sc[BG_R][BG_KS], sr[BG_R][BG_KS];
+#pragma unroll
+        for (int k = 0; k < BG_R; ++k)
+#pragma unroll
+            for (int e = 0; e < BG_KS; ++e) {
+                const int j = sj[k][e] >= 0 ? sj[k][e] : 0;
+                st[k][e] = T[(size_t)ir[k] * (size_t)n + j];
+                sc[k][e] = (double)C[(size_t)ir[k] * (size_t)n + j];
+                sr[k][e] = rg[j];
+            }
+        double best[BG_R];
+        int bj[BG_R];
+#pragma unroll
+        for (int k = 0; k < BG_R; ++k) { best[k] = INFINITY; bj[k] = 0x7fffffff; }
+        for (int q0 = 0; q0 < nv; q0 += 64 * U) {
+            CV cv[BG_R][U];
+            double rv[U][VEC];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * 64 + lane;
+                const int qc = q < nv ? q : nv - 1;  // clamped: read, then masked
+#pragma unroll
+                for (int k = 0; k < BG_R; ++k)
+                    cv[k][u] = reinterpret_cast<const CV *>(C + (size_t)ir[k] * (size_t)n)[qc];
+                if constexpr (VEC == 4) {
+                    const double2 r0 = reinterpret_cast<const double2 *>(rg)[2 * qc];
+                    const double2 r1 = reinterpret_cast<const double2 *>(rg)[2 * qc + 1];
+                    rv[u][0] = r0.x; rv[u][1] = r0.y; rv[u][2] = r1.x; rv[u][3] = r1.y;
+                } else {
+                    rv[u][0] = rg[qc];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * 64 + lane;
+#pragma unroll
+                for (int k = 0; k < BG_R; ++k) {
+                    float c[VEC];
+                    if constexpr (VEC == 4) {
+                        c[0] = cv[k][u].x; c[1] = cv[k][u].y; c[2] = cv[k][u].z; c[3] = cv[k][u].w;
+                    } else {
+                        c[0] = cv[k][u];
+                    }
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const double v = q < nv ? (double)c[e] + w * rv[u][e] : INFINITY;
+                        if (v < best[k]) { best[k] = v; bj[k] = q * VEC + e; }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < BG_R; ++k) {
+            if (i0 + k >= m) break;  // uniform over the wave
+            const int i = i0 + k;
+            double G = best[k];
+            int J = bj[k];
+            wave_argmin(G, J);
+            double x[2] = {0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < BG_KS; ++e) {
+                if (sj[k][e] >= 0) {
+                    x[0] += st[k][e] * (sc[k][e] + w * sr[k][e] - G);
+                    x[1] += st[k][e] * sc[k][e];
+                }
+            }
+            if (__any(more[k])) {
+                // the lane's support entries after its first BG_KS, same order
+                int seen = 0;
+#pragma unroll
+                for (int q = 0; q < WPL; ++q) {
+                    uint32_t mk = mw[k][q];
+                    while (mk) {
+                        const int u = __ffs(mk) - 1;
+                        mk &= mk - 1u;
+                        if (seen++ < BG_KS) continue;
+                        const int j = owned_col<NT, VEC>(u, lane + 64 * q);
+                        const double t = T[(size_t)i * (size_t)n + j];
+                        const double c = (double)C[(size_t)i * (size_t)n + j];
+                        x[0] += t * (c + w * rg[j] - G);
+                        x[1] += t * c;
+                    }
+                }
+            }
+            wave_sum<2>(x);
+            aG += P.a[i] * G;
+            lin += x[1];
+            gs += x[0];
+        }
     }
     if (lane == 0) { s_w[wid][0] = aG; s_w[wid][1] = lin; s_w[wid][2] = gs; }
     double rb[2] = {0.0, 0.0};
+#pragma unroll 4
     for (int j = threadIdx.x; j < n; j += NT) {
         rb[0] += rg[j] * rg[j];
         rb[1] += P.b[j] * rg[j];
@@ -143,23 +257,17 @@ __device__ void batch_gap(const ProblemView &P, const double *__restrict__ T,
     __syncthreads();  // s_w and s_rb are rewritten by the next sweep
 }
 
+// One problem from its initial plan to the stop test, by the workgroup.
 template <int NT, int CPT, int VEC>
-__global__ __launch_bounds__(NT) void batch_solve_kernel(const float *__restrict__ C,
-                                                         const double *__restrict__ a,
-                                                         const double *__restrict__ b,
-                                                         double *__restrict__ Tar,
-                                                         double *__restrict__ rar,
-                                                         uint32_t *__restrict__ Mar,
-                                                         int32_t *__restrict__ idxar,
-                                                         const BatchProblem *__restrict__ probs,
-                                                         const int32_t *__restrict__ order,
-                                                         BatchParams prm,
-                                                         BatchResult *__restrict__ res)
+__device__ __forceinline__ void batch_solve_one(const float *__restrict__ C, const double *__restrict__ a,
+                                                const double *__restrict__ b, double *__restrict__ Tar,
+                                                double *__restrict__ rar, uint32_t *__restrict__ Mar,
+                                                int32_t *__restrict__ idxar, const BatchProblem &bp, int32_t p,
+                                                const BatchParams &prm, BatchResult *__restrict__ res)
 {
     constexpr int COST = SROT_COST_F32;
     const int tid = threadIdx.x;
-    const int p = order[blockIdx.x];
-    const BatchProblem bp = probs[p];
+    const uint64_t t_start = wall_clock64();
     ProblemView P;
     P.m = bp.m; P.n = bp.n; P.cost = COST;
     P.C = C + bp.c_off;
@@ -200,13 +308,14 @@ __global__ __launch_bounds__(NT) void batch_solve_kernel(const float *__restrict
         passes = pass + 1;
         if (passes % prm.gap_every == 0 || passes == prm.max_passes) {
             __syncthreads();  // the sweep reads every thread's columns of r, T and the masks
-            batch_gap<NT, VEC>(P, T, rg, M, g, f, D);
+            batch_gap<NT, CPT, VEC>(P, T, rg, M, g, f, D);
             if (g <= prm.eps) { status = SROT_OK; break; }
         }
     }
     if (tid == 0) {
         BatchResult out;
         out.g = g; out.f = f; out.D = D; out.passes = passes; out.status = status; out.pad = 0;
+        out.ticks = (int64_t)(wall_clock64() - t_start);
         res[p] = out;
     }
 }
@@ -249,24 +358,72 @@ struct Tile {
     bool operator==(const Tile &o) const { return nt == o.nt && cpt == o.cpt && vec == o.vec; }
 };
 
-// Tile shapes compiled for the batched kernel (one mask word per thread).
+// Tile shapes compiled for the batched kernel (one mask word per thread),
+// numbered in this order.
 #define SROT_BATCH_TILES(X) \
-    X(64, 2, 1) X(64, 4, 1) X(128, 4, 1) X(256, 4, 1) X(256, 8, 1) X(256, 16, 1) \
-    X(64, 4, 4) X(128, 4, 4) X(256, 4, 4) X(256, 8, 4) X(256, 16, 4)
+    X(0, 64, 2, 1) X(1, 64, 4, 1) X(2, 128, 4, 1) X(3, 256, 4, 1) X(4, 256, 8, 1) X(5, 256, 16, 1) \
+    X(6, 64, 4, 4) X(7, 128, 4, 4) X(8, 256, 4, 4) X(9, 256, 8, 4) X(10, 256, 16, 4)
 
-const void *batch_kernel_for(const Tile &t)
+int tile_id(const Tile &t)
 {
-#define SROT_BK(NT_, CPT_, VEC_) \
-    if (t.nt == NT_ && t.cpt == CPT_ && t.vec == VEC_) return (const void *)&batch_solve_kernel<NT_, CPT_, VEC_>;
-    SROT_BATCH_TILES(SROT_BK)
-#undef SROT_BK
-    return nullptr;
+#define SROT_TID(ID_, NT_, CPT_, VEC_) \
+    if (t.nt == NT_ && t.cpt == CPT_ && t.vec == VEC_) return ID_;
+    SROT_BATCH_TILES(SROT_TID)
+#undef SROT_TID
+    return -1;
+}
+
+// Launch classes: the tiles of one class share a kernel (and its
+// workgroup size), which picks the problem's tile at run time.  Four
+// classes keep the whole batch within four concurrent launches.
+constexpr int kClasses = 4;
+int tile_class(const Tile &t) { return t.nt == 64 ? 0 : t.nt == 128 ? 1 : t.vec == 1 ? 2 : 3; }
+constexpr int class_nt(int c) { return c == 0 ? 64 : c == 1 ? 128 : 256; }
+
+// A workgroup per problem: order[blockIdx.x] names it, its tile id (one of
+// the class's) selects the instantiation.
+template <int NT, int V4>
+__global__ __launch_bounds__(NT) void batch_solve_kernel(const float *__restrict__ C,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         double *__restrict__ Tar,
+                                                         double *__restrict__ rar,
+                                                         uint32_t *__restrict__ Mar,
+                                                         int32_t *__restrict__ idxar,
+                                                         const BatchProblem *__restrict__ probs,
+                                                         const int32_t *__restrict__ order,
+                                                         BatchParams prm,
+                                                         BatchResult *__restrict__ res)
+{
+    const int32_t p = order[blockIdx.x];
+    const BatchProblem bp = probs[p];
+    switch (bp.tile) {
+#define SROT_BCASE(ID_, NT_, CPT_, VEC_)                                                      \
+    case ID_:                                                                                \
+        if constexpr (NT_ == NT && (NT != 256 || (VEC_ == 4) == (V4 != 0)))                  \
+            batch_solve_one<NT_, CPT_, VEC_>(C, a, b, Tar, rar, Mar, idxar, bp, p, prm, res); \
+        break;
+        SROT_BATCH_TILES(SROT_BCASE)
+#undef SROT_BCASE
+    default:
+        break;
+    }
+}
+
+const void *class_kernel(int c)
+{
+    switch (c) {
+    case 0: return (const void *)&batch_solve_kernel<64, 0>;
+    case 1: return (const void *)&batch_solve_kernel<128, 0>;
+    case 2: return (const void *)&batch_solve_kernel<256, 0>;
+    default: return (const void *)&batch_solve_kernel<256, 1>;
+    }
 }
 
 std::vector<Tile> tile_candidates(int64_t n, bool vec4)
 {
     std::vector<Tile> out;
-#define SROT_BC(NT_, CPT_, VEC_) \
+#define SROT_BC(ID_, NT_, CPT_, VEC_) \
     if ((int64_t)NT_ * CPT_ >= n && (VEC_ == 1 || vec4)) out.push_back(Tile{NT_, CPT_, VEC_});
     SROT_BATCH_TILES(SROT_BC)
 #undef SROT_BC
@@ -298,6 +455,9 @@ struct srot_batch {
     std::vector<Tile> tile;                 // per problem
     std::vector<std::pair<Tile, std::pair<int, int>>> groups;  // tile, (first, count) in the order array
     std::vector<float> tune_ms;             // per group: measured ms per block step (0 = not tuned)
+    std::vector<int32_t> order;             // launch order: the classes' segments back to back
+    int cls_first[srot::kClasses] = {}, cls_count[srot::kClasses] = {};
+    int tune_cached = 0;                    // groups whose tile came from the tuning cache
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -356,11 +516,9 @@ BatchParams params_of(const srot_options &o)
     return prm;
 }
 
-hipError_t launch_group(srot_batch *h, const Tile &t, int first, int cnt, const BatchParams &prm,
-                        hipStream_t st)
+hipError_t launch_class(srot_batch *h, int cls, int first, int cnt, const BatchParams &prm, hipStream_t st)
 {
-    const void *fn = srot::batch_kernel_for(t);
-    if (!fn) return hipErrorInvalidDeviceFunction;
+    const void *fn = srot::class_kernel(cls);
     const float *C = h->C;
     const double *a = h->a, *b = h->b;
     double *T = h->T, *r = h->r;
@@ -368,21 +526,79 @@ hipError_t launch_group(srot_batch *h, const Tile &t, int first, int cnt, const 
     int32_t *idx = h->idx;
     const BatchProblem *probs = h->d_probs;
     const int32_t *order = h->d_order + first;
-    BatchResult *res = h->d_res;
     BatchParams pr = prm;
+    BatchResult *res = h->d_res;
     void *args[] = {&C, &a, &b, &T, &r, &M, &idx, &probs, &order, &pr, &res};
-    return hipLaunchKernel(fn, dim3(cnt), dim3(t.nt), args, 0, st);
+    return hipLaunchKernel(fn, dim3(cnt), dim3(srot::class_nt(cls)), args, 0, st);
+}
+
+// Tuning cache: the tile chosen for a group, keyed by the group's default
+// tile, its widest row and whether its rows allow 16-byte loads (the
+// candidates depend on these alone), with the measured time per block step.
+// Kept for the process, and in a file of JSON lines when SROT_TUNE_CACHE
+// names one: read at the first tuned init, a line appended per new entry.
+struct TuneEntry {
+    Tile tile;
+    float ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Tile &dflt, int64_t nmax, bool vec4)
+{
+    char buf[128];
+    snprintf(buf, sizeof(buf), "gfx950/%dx%dx%d/n%lld/v%d", dflt.nt, dflt.cpt, dflt.vec, (long long)nmax,
+             vec4 ? 1 : 0);
+    return buf;
+}
+
+void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("SROT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        char key[256];
+        int nt = 0, cpt = 0, vec = 0;
+        float ms = 0.0f;
+        if (sscanf(line, "{\"key\": \"%255[^\"]\", \"nt\": %d, \"cpt\": %d, \"vec\": %d, \"ms\": %f}", key, &nt,
+                   &cpt, &vec, &ms) == 5) {
+            const Tile t{nt, cpt, vec};
+            if (srot::tile_id(t) >= 0) g_tune[key] = TuneEntry{t, ms};
+        }
+    }
+    fclose(f);
+}
+
+void tune_cache_store(const std::string &key, const TuneEntry &e)
+{
+    g_tune[key] = e;
+    const char *path = getenv("SROT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": \"%s\", \"nt\": %d, \"cpt\": %d, \"vec\": %d, \"ms\": %.6g}\n", key.c_str(), e.tile.nt,
+            e.tile.cpt, e.tile.vec, e.ms);
+    fclose(f);
 }
 
 // Milliseconds per block step of one tile on the problem at position `pos`
-// of the launch order: two passes and a gap sweep from the initial plan (the
-// second of two runs).
+// of the launch order: one pass and a gap sweep from the initial plan,
+// timed on the second of two runs.
 int time_tile(srot_batch *h, int pos, int32_t p, const Tile &t, float *ms_per_step)
 {
     BatchParams prm = params_of(h->opt);
-    prm.max_passes = 2;
-    prm.gap_every = 2;
+    prm.max_passes = 1;
+    prm.gap_every = 1;
     prm.eps = -1.0;
+    h->probs[p].tile = srot::tile_id(t);
+    SROT_HIP_B(hipMemcpyAsync(h->d_probs + p, &h->probs[p], sizeof(BatchProblem), hipMemcpyHostToDevice,
+                              h->stream));
     hipEvent_t e0, e1;
     SROT_HIP_B(hipEventCreate(&e0));
     SROT_HIP_B(hipEventCreate(&e1));
@@ -390,7 +606,7 @@ int time_tile(srot_batch *h, int pos, int32_t p, const Tile &t, float *ms_per_st
     int rc = SROT_OK;
     for (int rep = 0; rep < 2 && rc == SROT_OK; ++rep) {
         hipError_t e = hipEventRecord(e0, h->stream);
-        if (e == hipSuccess) e = launch_group(h, t, pos, 1, prm, h->stream);
+        if (e == hipSuccess) e = launch_class(h, srot::tile_class(t), pos, 1, prm, h->stream);
         if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -400,7 +616,7 @@ int time_tile(srot_batch *h, int pos, int32_t p, const Tile &t, float *ms_per_st
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *ms_per_step = best / (float)(2 * h->probs[p].m);
+    *ms_per_step = best / (float)h->probs[p].m;
     return rc;
 }
 
@@ -461,11 +677,13 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
         if (bp.c_off < 0) { delete h; return fail(SROT_EINVAL, "srot_init_batched: negative c_off"); }
         cc += m[p] * n[p];
         ca += m[p]; cb += n[p];
-        h->probs.push_back(bp);
         const bool vec4 = (n[p] % 4 == 0) && (bp.c_off % 4 == 0) && (((uintptr_t)C) % 16 == 0);
         const srot::Ownership o = srot::choose_ownership(n[p], SROT_COST_F32, vec4);
         Tile t{o.nt, o.cpt, o.vec};
-        if (!srot::batch_kernel_for(t)) t = Tile{256, 16, 1};  // any n <= 4096 fits
+        if (srot::tile_id(t) < 0) t = Tile{256, 16, 1};  // any n <= 4096 fits
+        bp.tile = srot::tile_id(t);
+        bp.pad = 0;
+        h->probs.push_back(bp);
         h->tile.push_back(t);
     }
     // problems of one default tile form a group; in it the largest go first
@@ -500,48 +718,88 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
     if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init_batched: %s", hipGetErrorString(e));
     else if (flag & 1) rc = fail(SROT_ENONFINITE, "srot_init_batched: NaN/Inf in C, a or b, or a negative weight");
 
-    // autotuner: per group, time every candidate tile on the group's largest problem
+    // autotuner: per group, time every candidate tile on the group's largest
+    // problem, unless the tuning cache holds the group's size class
     h->tune_ms.assign(h->groups.size(), 0.0f);
+    h->tune_cached = 0;
+    std::unique_lock<std::mutex> lock(g_tune_mu, std::defer_lock);
+    if (tune) {
+        lock.lock();
+        tune_cache_load();
+    }
     for (size_t gi = 0; rc == SROT_OK && tune && gi < h->groups.size(); ++gi) {
         const int first = h->groups[gi].second.first, cnt = h->groups[gi].second.second;
         const int p0 = ord[first];
         int64_t nmax = 0;
         bool vec4 = h->groups[gi].first.vec == 4;
         for (int q = first; q < first + cnt; ++q) nmax = std::max<int64_t>(nmax, h->probs[ord[q]].n);
+        const std::string key = tune_key(h->groups[gi].first, nmax, vec4);
         Tile best = h->groups[gi].first;
         float best_ms = 0.0f;
-        for (const Tile &t : srot::tile_candidates(nmax, vec4)) {
-            float ms = 0.0f;
-            rc = time_tile(h, first, p0, t, &ms);
-            if (rc != SROT_OK) break;
-            if (best_ms == 0.0f || ms < best_ms) { best_ms = ms; best = t; }
+        auto hit = g_tune.find(key);
+        if (hit != g_tune.end()) {
+            best = hit->second.tile;
+            best_ms = hit->second.ms;
+            h->tune_cached += 1;
+        } else {
+            for (const Tile &t : srot::tile_candidates(nmax, vec4)) {
+                float ms = 0.0f;
+                rc = time_tile(h, first, p0, t, &ms);
+                if (rc != SROT_OK) break;
+                if (best_ms == 0.0f || ms < best_ms) { best_ms = ms; best = t; }
+            }
+            if (rc == SROT_OK) tune_cache_store(key, TuneEntry{best, best_ms});
         }
         h->groups[gi].first = best;
         h->tune_ms[gi] = best_ms;
-        for (int q = first; q < first + cnt; ++q) h->tile[ord[q]] = best;
+        for (int q = first; q < first + cnt; ++q) {
+            h->tile[ord[q]] = best;
+            h->probs[ord[q]].tile = srot::tile_id(best);
+        }
+    }
+    if (lock.owns_lock()) lock.unlock();
+
+    // launch order: per class, the largest problems first (each solve then
+    // reorders by the measured run times)
+    for (int c = 0; c < srot::kClasses; ++c) {
+        h->cls_first[c] = (int)h->order.size();
+        for (int32_t p : ord)
+            if (srot::tile_class(h->tile[p]) == c) h->order.push_back(p);
+        h->cls_count[c] = (int)h->order.size() - h->cls_first[c];
+        std::stable_sort(h->order.begin() + h->cls_first[c], h->order.end(), [&](int32_t x, int32_t y) {
+            return (int64_t)h->probs[x].m * h->probs[x].n > (int64_t)h->probs[y].m * h->probs[y].n;
+        });
+    }
+    if (rc == SROT_OK) {
+        e = hipMemcpyAsync(h->d_probs, h->probs.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice,
+                           h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_order, h->order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice,
+                               h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init_batched: %s", hipGetErrorString(e));
     }
 
-    // one graph: a kernel node per group, no dependencies between them
+    // one graph: a kernel node per class, no dependencies between them
     if (rc == SROT_OK) {
         e = hipGraphCreate(&h->graph, 0);
         const BatchParams prm = params_of(h->opt);
-        for (size_t gi = 0; e == hipSuccess && gi < h->groups.size(); ++gi) {
-            const Tile &t = h->groups[gi].first;
-            const int first = h->groups[gi].second.first, cnt = h->groups[gi].second.second;
+        for (int c = 0; e == hipSuccess && c < srot::kClasses; ++c) {
+            if (h->cls_count[c] == 0) continue;
             const float *Cp = h->C;
             const double *ap = h->a, *bp = h->b;
             double *Tp = h->T, *rp = h->r;
             uint32_t *Mp = h->M;
             int32_t *ip = h->idx;
             const BatchProblem *pp = h->d_probs;
-            const int32_t *op = h->d_order + first;
+            const int32_t *op = h->d_order + h->cls_first[c];
             BatchParams pr = prm;
             BatchResult *resp = h->d_res;
             void *args[] = {&Cp, &ap, &bp, &Tp, &rp, &Mp, &ip, &pp, &op, &pr, &resp};
             hipKernelNodeParams kp{};
-            kp.func = const_cast<void *>(srot::batch_kernel_for(t));
-            kp.gridDim = dim3(cnt);
-            kp.blockDim = dim3(t.nt);
+            kp.func = const_cast<void *>(srot::class_kernel(c));
+            kp.gridDim = dim3(h->cls_count[c]);
+            kp.blockDim = dim3(srot::class_nt(c));
             kp.sharedMemBytes = 0;
             kp.kernelParams = args;
             kp.extra = nullptr;
@@ -575,6 +833,18 @@ int srot_solve_batched(srot_batch *h, double *out3, int64_t *passes, int32_t *st
         if (passes) passes[p] = res[p].passes;
         if (status) status[p] = res[p].status;
         all &= (res[p].status == SROT_OK);
+    }
+    // the next solve starts each class's longest-running problems first
+    // (the results do not depend on the order)
+    std::vector<int32_t> next = h->order;
+    for (int c = 0; c < srot::kClasses; ++c)
+        std::stable_sort(next.begin() + h->cls_first[c], next.begin() + h->cls_first[c] + h->cls_count[c],
+                         [&](int32_t x, int32_t y) { return res[x].ticks > res[y].ticks; });
+    if (next != h->order) {
+        h->order = next;
+        SROT_HIP_B(hipMemcpyAsync(h->d_order, h->order.data(), sizeof(int32_t) * h->count, hipMemcpyHostToDevice,
+                                  h->stream));
+        SROT_HIP_B(hipStreamSynchronize(h->stream));
     }
     return all ? SROT_OK : SROT_NOT_CONVERGED;
 }
