@@ -370,8 +370,9 @@ size_t srot_workspace_size_batched(int32_t count, const int64_t *m, const int64_
  *   opt      host; cost must be SROT_COST_F32, sampling SROT_UNIFORM.
  *   tune     0: each problem gets the tile shape srot_init would choose;
  *            1: per group of problems sharing that shape, every compiled
- *            candidate shape is timed on the group's largest problem (one
- *            pass, second of two runs) and the fastest is kept.  Choices
+ *            candidate shape is timed on the group's widest problem with
+ *            the fewest rows (one pass, second of two runs) and the
+ *            fastest is kept.  Choices
  *            are cached per size class (default shape, widest row,
  *            16-byte rows) for the process, and in the file of JSON lines
  *            named by the environment variable SROT_TUNE_CACHE, if set

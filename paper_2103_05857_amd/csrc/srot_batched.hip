@@ -11,7 +11,7 @@
 //
 // Each problem has a tile shape (threads x columns per thread x vector
 // width): either the single-problem default for its width or, with
-// srot_init_batched(tune = 1), the fastest candidate measured on the largest
+// srot_init_batched(tune = 1), the fastest candidate measured on the widest
 // problem of its default shape.  Shapes of one workgroup size (and, at 256
 // threads, one vector width) form a launch class: one launch of
 // batch_solve_kernel per class, one workgroup per problem, which switches
@@ -718,8 +718,10 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
     if (e != hipSuccess) rc = fail(SROT_EHIP, "srot_init_batched: %s", hipGetErrorString(e));
     else if (flag & 1) rc = fail(SROT_ENONFINITE, "srot_init_batched: NaN/Inf in C, a or b, or a negative weight");
 
-    // autotuner: per group, time every candidate tile on the group's largest
-    // problem, unless the tuning cache holds the group's size class
+    // autotuner: per group, time every candidate tile on the group's widest
+    // problem with the fewest rows (the time per block step follows the row
+    // width; a pass is m steps), unless the tuning cache holds the group's
+    // size class
     h->tune_ms.assign(h->groups.size(), 0.0f);
     h->tune_cached = 0;
     std::unique_lock<std::mutex> lock(g_tune_mu, std::defer_lock);
@@ -729,7 +731,12 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
     }
     for (size_t gi = 0; rc == SROT_OK && tune && gi < h->groups.size(); ++gi) {
         const int first = h->groups[gi].second.first, cnt = h->groups[gi].second.second;
-        const int p0 = ord[first];
+        int pos0 = first;
+        for (int q = first + 1; q < first + cnt; ++q) {
+            const BatchProblem &x = h->probs[ord[q]], &y = h->probs[ord[pos0]];
+            if (x.n > y.n || (x.n == y.n && x.m < y.m)) pos0 = q;
+        }
+        const int p0 = ord[pos0];
         int64_t nmax = 0;
         bool vec4 = h->groups[gi].first.vec == 4;
         for (int q = first; q < first + cnt; ++q) nmax = std::max<int64_t>(nmax, h->probs[ord[q]].n);
@@ -744,7 +751,7 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
         } else {
             for (const Tile &t : srot::tile_candidates(nmax, vec4)) {
                 float ms = 0.0f;
-                rc = time_tile(h, first, p0, t, &ms);
+                rc = time_tile(h, pos0, p0, t, &ms);
                 if (rc != SROT_OK) break;
                 if (best_ms == 0.0f || ms < best_ms) { best_ms = ms; best = t; }
             }
