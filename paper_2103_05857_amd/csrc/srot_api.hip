@@ -417,8 +417,16 @@ int srot_gap(srot_handle *h, double *out3, double *row_gap, int32_t *row_argmin)
 int srot_gap_async(srot_handle *h, double *out5)
 {
     if (!h || !out5) return fail(SROT_EINVAL, "srot_gap_async: NULL argument");
-    SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
-    SROT_HIP(hipMemcpyAsync(out5, h->S.scalars, sizeof(double) * 5, hipMemcpyDefault, h->stream));
+    // device memory is written by the final-sum kernel itself; host memory
+    // gets a copy
+    hipPointerAttribute_t at{};
+    int dev = -1;
+    const bool on_device = hipPointerGetAttributes(&at, out5) == hipSuccess && at.type == hipMemoryTypeDevice &&
+                           hipGetDevice(&dev) == hipSuccess && at.device == dev;
+    (void)hipGetLastError();  // a host pointer unknown to HIP is not an error here
+    SROT_HIP(srot::launch_gap(h->P, h->S, h->stream, on_device ? out5 : nullptr));
+    if (!on_device)
+        SROT_HIP(hipMemcpyAsync(out5, h->S.scalars, sizeof(double) * 5, hipMemcpyDefault, h->stream));
     return SROT_OK;
 }
 

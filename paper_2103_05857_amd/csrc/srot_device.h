@@ -886,4 +886,60 @@ __device__ __forceinline__ uint64_t philox_output(uint64_t seed, uint64_t k)
     return c[k & 3];
 }
 
+// ---------------------------------------------------------------------------
+// The final sums of a gap sweep over its nb workgroup partials (component
+// c of workgroup k at partials[c * nb + k]), by a workgroup of GAP_FINAL_NT
+// threads in a fixed order: thread t adds workgroups t, t + GAP_FINAL_NT,
+// ... (all requested at once), then the wave (DPP), then the waves in
+// order; thread 0 writes
+//   out[0] = g, out[1] = f, out[2] = D, out[3] = <T,C>, out[4] = ||r||^2
+// and the same into out2 when given.
+// ---------------------------------------------------------------------------
+constexpr int GAP_FINAL_NT = 1024;
+
+__device__ __forceinline__ void gap_total(double w, const double *__restrict__ partials, int nb,
+                                          double *__restrict__ out, double *__restrict__ out2 = nullptr)
+{
+    constexpr int PER = GAP_MAX_BLOCKS / GAP_FINAL_NT;  // workgroups per thread
+    constexpr int NW = GAP_FINAL_NT / 64;
+    __shared__ double s_red[NW * 5];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double v[PER][5];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int k = tid + q * GAP_FINAL_NT;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[q][c] = (k < nb) ? partials[c * nb + k] : 0.0;
+    }
+    double f5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // a_i G_i, lin, g, ||r||^2, <b, r>
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) f5[c] += v[q][c];
+    }
+    wave_sum<5>(f5);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s_red[wid * 5 + c] = f5[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t5[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            t5[c] = s_red[c];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) t5[c] += s_red[q * 5 + c];
+        }
+        const double pa = t5[0], pl = t5[1], pg = t5[2], rr = t5[3], br = t5[4];
+        const double o5[5] = {pg, pl + 0.5 * w * rr, pa - w * br - 0.5 * w * rr, pl, rr};
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = o5[c];
+        if (out2) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) out2[c] = o5[c];
+        }
+    }
+}
+
 }  // namespace srot

@@ -1,15 +1,16 @@
 // Full Frank-Wolfe (Alg. A.1, step eq. AppenEq:SemiRelaxedFWStep) on the
-// handle's plan, for gfx950.  An iteration is one gap-sweep launch in its
-// FW form (srot_kernels.hip): the sweep applies the previous iteration's
-// step to each row as it reaches it, measures every row's LMO vertex j*_i
-// and the gap g = <T - S, grad f> at the new plan, and adds a_i to the
-// vertex column sum s_{j*_i} in fixed point (integer atomics, so the sums do
-// not depend on the order the rows finish in); its last workgroup takes the
-// line search on d = r + b - s (or the decay rule), writes the residual of
-// the new plan and leaves the row updates to the next sweep, or stops when
-// g <= eps.  Here: the reset before a run (state, s, the fixed-point scale
-// of a) and the flush after it (a pending step applied to every row).  The
-// host is not involved between iterations.
+// handle's plan, for gfx950.  An iteration is two launches.  The gap sweep
+// in its FW form (srot_kernels.hip) applies the previous iteration's step
+// to each row as it reaches it, measures every row's LMO vertex j*_i and
+// its part of the gap g = <T - S, grad f> at the new plan, and adds a_i to
+// the vertex column sum s_{j*_i} in fixed point (integer atomics, so the
+// sums do not depend on the order the rows finish in).  The step kernel
+// (one workgroup) adds the sweep's partial sums, then takes the line search
+// on d = r + b - s (or the decay rule), writes the residual of the new plan
+// and leaves the row updates to the next sweep, or stops when g <= eps.
+// Here also: the reset before a run (state, s, the fixed-point scale of a)
+// and the flush after it (a pending step applied to every row).  The host
+// is not involved between iterations.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -56,8 +57,9 @@ __global__ __launch_bounds__(FW_NT) void fw_reset_kernel(int32_t m, int32_t n, c
     }
 }
 
-// The step of Alg. A.1 after an FW sweep (that sweep's gap in scal[0], the
-// vertex column sums s in fixed point), by one workgroup: ||d||^2 with
+// The step of Alg. A.1 after an FW sweep (that sweep's nb workgroup
+// partials, the vertex column sums s in fixed point), by one workgroup: the
+// sweep's final sums into scal[0..4] (gap_total), ||d||^2 with
 // d = r + b - s (T^T 1 - S^T 1) in a fixed order, then either the stop of
 // the run (gap <= eps, or a measuring-only sweep) or the exact line search
 // gamma = clip(g / (w ||d||^2), 0, 1) (eq. AppenEq:SemiRelaxedFWStep) or the
@@ -77,11 +79,12 @@ __global__ __launch_bounds__(FW_STEP_NT) void fw_step_kernel(int32_t n, double w
                                                              unsigned long long *__restrict__ s_fixed,
                                                              const double *__restrict__ scale_p,
                                                              double *__restrict__ scal, int32_t *__restrict__ state,
+                                                             const double *__restrict__ partials, int32_t nb,
                                                              FwStepArgs A)
 {
     // up to FW_STEP_NT * TB columns the values stay in registers between
     // the two passes; wider rows read them again
-    constexpr int NW = FW_STEP_NT / 64, TB = 16;
+    constexpr int NW = FW_STEP_NT / 64, TB = 8;
     __shared__ double sh[NW];
     __shared__ double s_gam;
     __shared__ int s_stop;
@@ -105,6 +108,8 @@ __global__ __launch_bounds__(FW_STEP_NT) void fw_step_kernel(int32_t n, double w
     };
     load(tid);
     if (done) return;  // the run has reached its gap
+    static_assert(FW_STEP_NT == GAP_FINAL_NT, "the final sums take the whole workgroup");
+    gap_total(w, partials, nb, scal);  // thread 0 reads scal[0] below
     double x[1] = {0.0};
     for (int j0 = tid; j0 < n; j0 += FW_STEP_NT * TB) {
         if (j0 != tid) load(j0);
@@ -182,7 +187,8 @@ hipError_t launch_fw_reset(const ProblemView &P, const DeviceState &S, hipStream
 
 hipError_t launch_fw_iteration(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t st)
 {
-    hipError_t e = launch_gap_fw(P, S, fw, st);
+    int nb = 0;
+    hipError_t e = launch_gap_fw(P, S, fw, st, &nb);
     if (e != hipSuccess) return e;
     FwStepArgs A;
     A.eps = fw.eps;
@@ -191,7 +197,7 @@ hipError_t launch_fw_iteration(const ProblemView &P, const DeviceState &S, const
     A.k = fw.k;
     A.trace_gamma = fw.trace_gamma;
     hipLaunchKernelGGL(fw_step_kernel, dim3(1), dim3(FW_STEP_NT), 0, st, P.n, P.w, P.b, S.r, fw.s_fixed, fw.scale,
-                       S.scalars, fw.state, A);
+                       S.scalars, fw.state, (const double *)S.partials, nb, A);
     return hipGetLastError();
 }
 

@@ -85,7 +85,9 @@ hipError_t launch_sample_permute(uint64_t seed, int64_t p0, int64_t npasses, int
 hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_t *idx,
                         int64_t k0, int64_t nsteps, int rule, int32_t *trace_j,
                         double *trace_gamma, hipStream_t stream);
-hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+// The sweep and its final sums into S.scalars[0..4] (and out_dev[0..4],
+// device memory, when given).
+hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream, double *out_dev = nullptr);
 
 // Screened-LMO chain (srot_screen.hip): stored FP32 cost in the 256 x {8,16}
 // x 4 ownership.  launch_cost_bounds writes {max |c_ij|, max(sum a, max b)}
@@ -117,6 +119,12 @@ int32_t gap_blocks_for(int64_t m);
 // Block-step chain over a team of workgroups (srot_team.hip), rows of
 // 4097 .. 1024 * TEAM_MAX_MEMBERS columns, any cost; the default there
 // unless SROT_TEAM_CHAIN=0 is set in the environment at init.
+// Gap sweep: threads per workgroup and the most workgroups (partials) of one
+// sweep.
+constexpr int GAP_NT = 256;
+constexpr int GAP_NW = GAP_NT / 64;
+constexpr int GAP_MAX_BLOCKS = 2048;
+
 constexpr int TEAM_MAX_MEMBERS = 64;
 constexpr int TEAM_REC_STRIDE = 16;  // 64-bit words per member record (one 128-byte line)
 int team_members(int64_t n);
@@ -157,7 +165,8 @@ struct FwSweep {
     int64_t k;                      // FW iteration counter (decay rule 2/(k+2))
     double *trace_gamma;            // device, one entry, or null
 };
-hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream);
+// The sweep alone (its nb workgroup partials are left for gap_total).
+hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream, int *nb);
 // One FW iteration: the FW sweep and the step kernel.
 hipError_t launch_fw_iteration(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream);
 // Before a run of FW sweeps: done / pending / steps cleared, s zeroed, the

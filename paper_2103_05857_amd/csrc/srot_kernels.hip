@@ -526,37 +526,29 @@ __global__ __launch_bounds__(256) void screen_bounds_kernel(ProblemView P, doubl
 // keeps the lowest index; 16 columns per lane are requested at once for each
 // of the R rows, and each r_j (read through L2, vectorised) serves the R
 // rows.  Per-row outputs go to row_G / row_j / row_g.  Row sums are added in
-// row order within a wave and waves in order within a workgroup; the last
-// workgroup to finish (ticket counter, reset by that workgroup) adds the
-// workgroup partials in a fixed tree order and writes
+// row order within a wave and waves in order within a workgroup; each
+// workgroup stores its partials, and gap_total (a one-workgroup kernel
+// after the sweep, or the first part of the full-FW step kernel) adds them
+// in a fixed tree order and writes
 //   out[0] = g = sum g_i,  out[1] = f = <T,C> + (w/2)||r||^2,
 //   out[2] = D = sum a_i G_i - w <b, r> - (w/2)||r||^2,  out[3] = <T,C>,
 //   out[4] = ||r||^2
 // (sum_i <t_i, grad_i f> = <T,C> + w <r + b, r> gives D = f - g).
 // ---------------------------------------------------------------------------
-constexpr int GAP_NT = 256;
-constexpr int GAP_NW = GAP_NT / 64;
-constexpr int GAP_MAX_BLOCKS = 2048;
 constexpr int GAP_KS = 2;  // support entries per lane and row gathered ahead of the scan
 
-// Workgroup partials of a gap sweep and the final sums.  Each workgroup adds
-// its rows' (a_i G_i, lin_i, g_i) and, for its slice of ceil(n / grid)
-// columns, ||r||^2 and <b, r>; the five partials travel through device-scope
-// atomics (performed at the coherent level, so no cache write-back is
-// needed), and the last workgroup to finish adds them in a fixed order: each
-// thread its strided workgroups (all requested at once), then the wave
-// (DPP), then the four waves in order.  At most GAP_MAX_BLOCKS workgroups.
-__device__ __forceinline__ void gap_finish(const ProblemView &P, const double *__restrict__ rg, double aG,
-                                           double lin, double gs, double *__restrict__ partials,
-                                           int32_t *__restrict__ ticket, double *__restrict__ out)
+// Workgroup partials of a gap sweep.  Each workgroup adds its rows'
+// (a_i G_i, lin_i, g_i) and, for its slice of ceil(n / grid) columns,
+// ||r||^2 and <b, r>, and stores the five component-major (component c of
+// workgroup b at partials[c * grid + b], so the final sum reads each
+// component contiguously); the sweep kernel ends there, and gap_total (the
+// next kernel) adds them.
+__device__ __forceinline__ void gap_partials(const ProblemView &P, const double *__restrict__ rg, double aG,
+                                             double lin, double gs, double *__restrict__ partials)
 {
-    constexpr int PER = GAP_MAX_BLOCKS / GAP_NT;  // workgroups per thread in the final sum
     __shared__ double s_w[GAP_NW][5];
-    __shared__ double s_red[GAP_NW * 5];
-    __shared__ int s_last;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int n = P.n;
-    const double w = P.w;
     const int nb = (int)gridDim.x;
     const int cols = (n + nb - 1) / nb;
     const int j0 = min(n, (int)blockIdx.x * cols), j1 = min(n, j0 + cols);
@@ -569,68 +561,19 @@ __device__ __forceinline__ void gap_finish(const ProblemView &P, const double *_
     wave_sum<2>(x);
     if (lane == 0) { s_w[wid][0] = aG; s_w[wid][1] = lin; s_w[wid][2] = gs; s_w[wid][3] = x[0]; s_w[wid][4] = x[1]; }
     __syncthreads();
-    // The ticket increment takes an operand computed from the values the
-    // exchanges return, so it is issued only after every partial has landed.
-    if (tid == 0) {
-        double t5[5];
+    if (tid < 5) {
+        double t = s_w[0][tid];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            t5[c] = s_w[0][c];
-#pragma unroll
-            for (int k = 1; k < GAP_NW; ++k) t5[c] += s_w[k][c];
-        }
-        unsigned long long seen = 0ull;
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-            seen ^= __hip_atomic_exchange(reinterpret_cast<unsigned long long *>(partials) + 8 * blockIdx.x + c,
-                                          (unsigned long long)__double_as_longlong(t5[c]), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        int zero;
-        asm volatile("v_mov_b32 %0, 0" : "=v"(zero) : "v"((unsigned)(seen ^ (seen >> 32))));
-        const int got = __hip_atomic_fetch_add(ticket, 1 + zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (got == nb - 1);
+        for (int k = 1; k < GAP_NW; ++k) t += s_w[k][tid];
+        partials[tid * nb + (int)blockIdx.x] = t;
     }
-    __syncthreads();
-    if (!s_last) return;
-    double v[PER][5];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int k = tid + q * GAP_NT;
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-            v[q][c] = (k < nb) ? __longlong_as_double((long long)__hip_atomic_load(
-                                     reinterpret_cast<unsigned long long *>(partials) + 8 * k + c, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT))
-                               : 0.0;
-    }
-    double f5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // a_i G_i, lin, g, ||r||^2, <b, r>
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) f5[c] += v[q][c];
-    }
-    wave_sum<5>(f5);
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) s_red[wid * 5 + c] = f5[c];
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t5[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            t5[c] = s_red[c];
-#pragma unroll
-            for (int q = 1; q < GAP_NW; ++q) t5[c] += s_red[q * 5 + c];
-        }
-        const double pa = t5[0], pl = t5[1], pg = t5[2], rr = t5[3], br = t5[4];
-        out[0] = pg;
-        out[1] = pl + 0.5 * w * rr;
-        out[2] = pa - w * br - 0.5 * w * rr;
-        out[3] = pl;
-        out[4] = rr;
-        __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+}
+
+__global__ __launch_bounds__(GAP_FINAL_NT) void gap_final_kernel(ProblemView P, const double *__restrict__ partials,
+                                                                 int nb, double *__restrict__ out,
+                                                                 double *__restrict__ out2)
+{
+    gap_total(P.w, partials, nb, out, out2);
 }
 
 template <int COST, int VEC, int R, bool FW>
@@ -641,7 +584,6 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double
                                                            int32_t *__restrict__ row_j,
                                                            double *__restrict__ row_g,
                                                            double *__restrict__ partials,
-                                                           int32_t *__restrict__ ticket,
                                                            double *__restrict__ out, FwSweep fw)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
@@ -837,7 +779,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double
             gs += x[0];
         }
     }
-    gap_finish(P, rg, aG, lin, gs, partials, ticket, out);
+    gap_partials(P, rg, aG, lin, gs, partials);
 }
 
 // Stored-cost gap sweep with the memory operations ordered for latency:
@@ -848,13 +790,18 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double
 // buffered (batch q + 1 requested before batch q is consumed).  Loads are
 // raw buffer loads whose out-of-range offsets return zero without touching
 // memory, so every batch is one fixed, branch-free group of requests and
-// each wait covers exactly the batch it needs.  Same per-row results and
-// summation order as gap_sweep_kernel.
+// each wait covers exactly the batch it needs.  Same per-row results as
+// gap_sweep_kernel (and, with R = 2, the same summation order).
+//
+// ROT (wide rows): each row group starts its column sweep at a hashed
+// vector offset and wraps around, so the waves in flight read different
+// parts of r at any moment instead of all requesting the same L2 lines; the
+// argmin then keeps the lowest index among equal values explicitly.
 constexpr int GAP_MW = 8;  // mask words per lane and row read ahead
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int COST, int R, int GU, bool FW>
+template <int COST, int R, int GU, bool FW, bool ROT>
 __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, double *__restrict__ T,
                                                             double *__restrict__ rg,
                                                             uint32_t *__restrict__ M, Ownership own,
@@ -862,7 +809,6 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
                                                             int32_t *__restrict__ row_j,
                                                             double *__restrict__ row_g,
                                                             double *__restrict__ partials,
-                                                            int32_t *__restrict__ ticket,
                                                             double *__restrict__ out, FwSweep fw)
 {
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
@@ -897,10 +843,17 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
         }
         u32x4 ca[R][GU], cb[R][GU];
         u32x4 ra[GU][RV], rb[GU][RV];
+        // vector group qq of the sweep order -> its place in the row
+        int rot = 0;
+        if constexpr (ROT) rot = (int)((((unsigned)(i0 / R) * 2654435761u) >> 8) % (unsigned)nq);
+        auto qmap = [&](int qq) {
+            if constexpr (!ROT) return qq;
+            return qq < nq ? (qq + rot >= nq ? qq + rot - nq : qq + rot) : nq;
+        };
         auto issue = [&](u32x4 (&c)[R][GU], u32x4 (&rr)[GU][RV], int q0) {
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
-                const int jb = ((q0 + u) * 64 + lane) * VEC;
+                const int jb = (qmap(q0 + u) * 64 + lane) * VEC;
                 const unsigned oc = jb < n ? (unsigned)jb * (unsigned)sizeof(CT) : kOOB;
                 const unsigned orr = jb < n ? (unsigned)jb * 8u : kOOB;
 #pragma unroll
@@ -917,7 +870,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
         auto consume = [&](const u32x4 (&c)[R][GU], const u32x4 (&rr)[GU][RV], int q0) {
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
-                const int jb = ((q0 + u) * 64 + lane) * VEC;
+                const int jb = (qmap(q0 + u) * 64 + lane) * VEC;
                 double rv[VEC];
 #pragma unroll
                 for (int h = 0; h < RV; ++h) {
@@ -937,22 +890,15 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
                             cval = __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
                         }
                         const double v = (jb < n) ? cval + w * rv[e] : INFINITY;
-                        if (v < best[k]) { best[k] = v; bj[k] = jb + e; }
+                        if (ROT ? (v < best[k] || (v == best[k] && jb + e < bj[k])) : (v < best[k])) {
+                            best[k] = v;
+                            bj[k] = jb + e;
+                        }
                     }
                 }
             }
         };
         issue(ca, ra, 0);
-        if constexpr (FW) {
-            // the previous iteration's step on these rows (their old
-            // vertices), while the first cost batch is on its way
-            if (pending) {
-#pragma unroll
-                for (int k = 0; k < R; ++k)
-                    if (i0 + k < m) fw_apply_row(i0 + k, n, gprev, P.a[i0 + k], row_j[i0 + k], own, T, M, lane, 64);
-                drain_memory();
-            }
-        }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             // rows past the end read an empty range: no support, no cost
@@ -964,17 +910,17 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
         }
 
         // support entries of the rows from the mask words (first GAP_KS per
-        // lane and row gathered now, further ones after the scan)
-        int sj[R][GAP_KS];
+        // lane and row gathered now, further ones after the scan); sq / sb
+        // keep each entry's mask word and bit
+        int sj[R][GAP_KS], sq[R][GAP_KS], sb[R][GAP_KS];
         double st[R][GAP_KS], sc[R][GAP_KS], sr[R][GAP_KS];
         bool more[R];
         int nfound[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
+        auto extract = [&](int k) {
             more[k] = false;
             int found = 0;
 #pragma unroll
-            for (int e = 0; e < GAP_KS; ++e) sj[k][e] = -1;
+            for (int e = 0; e < GAP_KS; ++e) { sj[k][e] = -1; sq[k][e] = 0; sb[k][e] = 0; }
             for (int q = 0; q < GAP_MW; ++q) {
                 uint32_t mk = mw[k][q];
                 const int sl = lane + 64 * q;
@@ -986,7 +932,11 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
                     const int j = ((u / own.vec) * own.nt + ts) * own.vec + (u % own.vec);
                     if (found < GAP_KS) {
 #pragma unroll
-                        for (int e = 0; e < GAP_KS; ++e) sj[k][e] = (e == found) ? j : sj[k][e];
+                        for (int e = 0; e < GAP_KS; ++e) {
+                            sj[k][e] = (e == found) ? j : sj[k][e];
+                            sq[k][e] = (e == found) ? q : sq[k][e];
+                            sb[k][e] = (e == found) ? b : sb[k][e];
+                        }
                         ++found;
                     } else {
                         more[k] = true;
@@ -995,6 +945,8 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
             }
             nfound[k] = found;
             more[k] |= (slots > 64 * GAP_MW) && (i0 + k < m);
+        };
+        auto gather = [&](int k) {
 #pragma unroll
             for (int e = 0; e < GAP_KS; ++e) {
                 const int j = sj[k][e] >= 0 ? sj[k][e] : 0;
@@ -1002,6 +954,80 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
                 sr[k][e] = rg[j];
                 sc[k][e] = (double)C[(size_t)ir[k] * (size_t)n + j];
             }
+        };
+#pragma unroll
+        for (int k = 0; k < R; ++k) extract(k);
+        if constexpr (FW) {
+            // the previous iteration's step on these rows (Alg. A.1:
+            // t_ij <- (1 - gamma) t_ij + gamma a_i [j == js], js the row's
+            // previous vertex), taken on the entries gathered here when each
+            // lane's part of the support, the vertex included, fits them;
+            // otherwise the row is updated in full first and read again
+            if (pending) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int i = i0 + k;
+                    if (i >= m) break;  // uniform over the wave
+                    const int js = row_j[i];
+                    const int jg = js / own.vec;
+                    const int u_star = (jg / own.nt) * own.vec + (js % own.vec);
+                    const int s_star = (u_star >> 5) * own.nt + jg % own.nt;
+                    const int q_star = s_star >> 6, b_star = u_star & 31;
+                    const bool mine = (s_star & 63) == lane;
+                    // js joins the lane's entries unless its bit is set already
+                    const bool add = mine && q_star < GAP_MW && !((mw[k][q_star < GAP_MW ? q_star : 0] >> b_star) & 1u);
+                    const bool over = more[k] || (add && nfound[k] >= GAP_KS) || (mine && q_star >= GAP_MW);
+                    if (__any(over)) {
+                        fw_apply_row(i, n, gprev, P.a[i], js, own, T, M, lane, 64);
+                        drain_memory();
+                        const __amdgpu_buffer_rsrc_t rs_m = buf_rsrc(M + (size_t)i * slots, (unsigned)slots * 4u);
+#pragma unroll
+                        for (int q = 0; q < GAP_MW; ++q)
+                            mw[k][q] = __builtin_amdgcn_raw_buffer_load_b32(rs_m, (int)((lane + 64 * q) * 4), 0, 0);
+                        extract(k);
+                        gather(k);
+                        continue;
+                    }
+                    if (add) {
+#pragma unroll
+                        for (int e = 0; e < GAP_KS; ++e) {
+                            const bool here = e == nfound[k];
+                            sj[k][e] = here ? js : sj[k][e];
+                            sq[k][e] = here ? q_star : sq[k][e];
+                            sb[k][e] = here ? b_star : sb[k][e];
+                        }
+                        ++nfound[k];
+                    }
+                    gather(k);
+                    const double gadd = gprev * P.a[i];
+                    uint32_t nm[GAP_MW];
+#pragma unroll
+                    for (int q = 0; q < GAP_MW; ++q) nm[q] = mw[k][q];
+#pragma unroll
+                    for (int e = 0; e < GAP_KS; ++e) {
+                        const int j = sj[k][e];
+                        if (j < 0) continue;
+                        const bool fresh = add && j == js;  // not in the support before
+                        const double t = fresh ? 0.0 : st[k][e];
+                        const double tn = (1.0 - gprev) * t + ((j == js) ? gadd : 0.0);
+                        if (tn != t || fresh) T[(size_t)i * (size_t)n + j] = tn;
+                        st[k][e] = tn;
+                        const uint32_t bit = 1u << sb[k][e];
+#pragma unroll
+                        for (int q = 0; q < GAP_MW; ++q)
+                            if (q == sq[k][e]) nm[q] = (tn != 0.0) ? (nm[q] | bit) : (nm[q] & ~bit);
+                    }
+#pragma unroll
+                    for (int q = 0; q < GAP_MW; ++q)
+                        if (nm[q] != mw[k][q]) M[(size_t)i * slots + lane + 64 * q] = nm[q];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k) gather(k);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) gather(k);
         }
 
         for (int q0 = 0; q0 < nq; q0 += 2 * GU) {
@@ -1061,7 +1087,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
             gs += x[0];
         }
     }
-    gap_finish(P, rg, aG, lin, gs, partials, ticket, out);
+    gap_partials(P, rg, aG, lin, gs, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -1423,63 +1449,87 @@ int32_t gap_blocks_for(int64_t m)
 // Row-strided sweep (fused cost, or rows not split into 16-byte vectors):
 // at most 1024 workgroups, where it measured best.
 template <int COST, int VEC>
-static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st)
+static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st,
+                                  int *nb_out)
 {
     constexpr int R = 2;  // each r_j read serves both rows
     const int64_t waves = (P.m + R - 1) / R;
     const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, 1024), S.gap_blocks);
+    *nb_out = nb;
     if (fw)
         hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R, true>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
-                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, *fw);
+                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, *fw);
     else
         hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R, false>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
-                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, FwSweep{});
+                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, FwSweep{});
     return hipGetLastError();
 }
 
 // Stored cost in 16-byte vectors: two rows per wave, double-buffered
-// batches of two vectors (FP32) or four (FP64) per lane and row.
-template <int COST>
-static hipError_t launch_gap_stream(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st)
+// batches of two vectors (FP32) or four (FP64) per lane and row; rows of
+// 8192 columns or more: rotated starts and, for the plain sweep, four rows
+// per wave, half the batch, at most 512 workgroups (measured best on
+// 16384 x 16384; the full-FW form keeps two rows per wave, which its
+// registers allow at two waves per SIMD).
+template <int COST, int R, int GU, bool ROT>
+static hipError_t launch_gap_stream_rg(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st,
+                                       int cap, int *nb_out)
 {
-    constexpr int R = 2, GU = (COST == SROT_COST_F32) ? 2 : 4;
     const int64_t waves = (P.m + R - 1) / R;
-    const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, GAP_MAX_BLOCKS),
-                                          S.gap_blocks);
+    const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, cap), S.gap_blocks);
+    *nb_out = nb;
     if (fw)
-        hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU, true>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
-                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, *fw);
+        hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU, true, ROT>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
+                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, *fw);
     else
-        hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU, false>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
-                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.flags + 4, S.scalars, FwSweep{});
+        hipLaunchKernelGGL((gap_stream_kernel<COST, R, GU, false, ROT>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
+                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, FwSweep{});
     return hipGetLastError();
 }
 
-static hipError_t launch_gap_any(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t stream)
+template <int COST>
+static hipError_t launch_gap_stream(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st,
+                                    int *nb_out)
+{
+    constexpr int GU = (COST == SROT_COST_F32) ? 2 : 4;
+    if (P.n >= 8192) {
+        if (fw) return launch_gap_stream_rg<COST, 2, GU, true>(P, S, fw, st, GAP_MAX_BLOCKS, nb_out);
+        return launch_gap_stream_rg<COST, 4, GU / 2, true>(P, S, fw, st, 512, nb_out);
+    }
+    return launch_gap_stream_rg<COST, 2, GU, false>(P, S, fw, st, GAP_MAX_BLOCKS, nb_out);
+}
+
+static hipError_t launch_gap_any(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t stream,
+                                 int *nb)
 {
     const uintptr_t cbase = (uintptr_t)P.C;
     // buffer ranges of one cost row and of r are 32-bit byte counts
     const bool ranged = (int64_t)P.n * 8 < (int64_t)0x7fffffff;
     switch (P.cost) {
     case SROT_COST_F32:
-        if (P.n % 4 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F32>(P, S, fw, stream);
-        return launch_gap_rows<SROT_COST_F32, 1>(P, S, fw, stream);
+        if (P.n % 4 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F32>(P, S, fw, stream, nb);
+        return launch_gap_rows<SROT_COST_F32, 1>(P, S, fw, stream, nb);
     case SROT_COST_F64:
-        if (P.n % 2 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F64>(P, S, fw, stream);
-        return launch_gap_rows<SROT_COST_F64, 1>(P, S, fw, stream);
+        if (P.n % 2 == 0 && cbase % 16 == 0 && ranged) return launch_gap_stream<SROT_COST_F64>(P, S, fw, stream, nb);
+        return launch_gap_rows<SROT_COST_F64, 1>(P, S, fw, stream, nb);
     default:
-        return launch_gap_rows<SROT_COST_SQEUCLID, 1>(P, S, fw, stream);
+        return launch_gap_rows<SROT_COST_SQEUCLID, 1>(P, S, fw, stream, nb);
     }
 }
 
-hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream)
+hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream, double *out_dev)
 {
-    return launch_gap_any(P, S, nullptr, stream);
+    int nb = 0;
+    hipError_t e = launch_gap_any(P, S, nullptr, stream, &nb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(GAP_FINAL_NT), 0, stream, P, (const double *)S.partials, nb,
+                       S.scalars, out_dev);
+    return hipGetLastError();
 }
 
-hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream)
+hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream, int *nb)
 {
-    return launch_gap_any(P, S, &fw, stream);
+    return launch_gap_any(P, S, &fw, stream, nb);
 }
 
 }  // namespace srot

@@ -239,7 +239,8 @@ def test_gap_sweep_on_given_plans(cost_mode, dtype):
     _need_gpu()
     rng = np.random.default_rng(3)
     shapes = [(1, 1, 1.0), (1, 9, 2.0), (17, 1, 0.5), (130, 257, 1.0), (64, 5003, 10.0),
-              (3, 4, 1.0), (5, 8, 2.0), (130, 256, 1.0), (64, 5004, 10.0), (6, 20000, 1.0)]
+              (3, 4, 1.0), (5, 8, 2.0), (130, 256, 1.0), (64, 5004, 10.0), (6, 20000, 1.0),
+              (41, 8192, 1.0), (23, 12000, 0.5)]
     for (m, n, w) in shapes:
         d = I.problem_mixture(7, m, n, cost_dtype=dtype)
         T = rng.random((m, n)) * (rng.random((m, n)) < 0.05)
@@ -253,6 +254,56 @@ def test_gap_sweep_on_given_plans(cost_mode, dtype):
         _close_fg((g, f, D), ref)
         np.testing.assert_array_equal(rj.cpu().numpy(), ref["jstar"])
         np.testing.assert_allclose(rg.cpu().numpy(), ref["grow"], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [4096, 8192, 12000])
+def test_gap_sweep_exact_ties_take_the_lowest_column(n):
+    """Rows whose minimum of c_ij + w r_j is attained exactly at three
+    columns far apart (r equal there: no plan mass, uniform b): the sweep
+    reports the lowest of them, also where rows start their column sweep at
+    a rotated offset (8192 columns and more)."""
+    _need_gpu()
+    m = 9
+    rng = np.random.default_rng(11)
+    C = (1.0 + rng.random((m, n))).astype(np.float32)
+    ties = np.stack([np.arange(m) + 100, np.arange(m) + n // 2 + 7, np.arange(m) + n - 40], axis=1)
+    for i in range(m):
+        C[i, ties[i]] = 0.25
+    a = np.full(m, 1.0 / m)
+    b = np.full(n, 1.0 / n)
+    T = np.zeros((m, n))
+    T[np.arange(m), (np.arange(m) * 37 + 1000) % n] = a  # away from the tied columns
+    d = {"a": a, "b": b, "C": C}
+    P = _oracle_problem(d, "stored", 1.0)
+    ref = O.gap(P, T)
+    np.testing.assert_array_equal(ref["jstar"], ties[:, 0])
+    sol = _gpu_problem(d, "stored", 1.0)
+    sol.set_state(torch.from_numpy(T).to(DEV), 0)
+    (g, f, D), rg, rj = sol.gap(per_row=True)
+    np.testing.assert_array_equal(rj.cpu().numpy(), ties[:, 0])
+    _close_fg((g, f, D), ref)
+    sol.close()
+
+
+def test_gap_async_into_device_and_pinned_memory():
+    """srot_gap_async: the final-sum kernel writes a device destination
+    itself, a pinned host one gets a copy; both equal srot_gap bitwise."""
+    _need_gpu()
+    S = _S()
+    for (m, n) in [(130, 256), (40, 8192), (33, 501)]:
+        d = I.problem_mixture(4, m, n)
+        sol = _gpu_problem(d, "stored", 1.0)
+        sol.step(3 * m)
+        ref = np.array(sol.gap())
+        dev5 = torch.full((5,), float("nan"), dtype=torch.float64, device=DEV)
+        host5 = torch.full((5,), float("nan"), dtype=torch.float64).pin_memory()
+        S.srot_gap_async(sol.h, dev5)
+        S.srot_gap_async(sol.h, host5)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(dev5.cpu().numpy()[:3], ref)
+        np.testing.assert_array_equal(host5.numpy()[:3], ref)
+        np.testing.assert_array_equal(dev5.cpu().numpy(), host5.numpy())
+        sol.close()
 
 
 def test_decay_rule_and_permutation_sampler():
