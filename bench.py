@@ -190,11 +190,11 @@ def main():
     gap_avg_ms = float(np.median(gap_ms))
     gap_bytes = 4.0 * m * n + 12.0 * nnz * m + 8.0 * (3 * m + n)
     gap_achieved = gap_bytes / (gap_avg_ms * 1e-3) / 1e9
-    gap_sweep = dict(kernel="gap_stream_kernel<f32,2,2>", bound="hbm",
+    gap_sweep = dict(kernel="gap_stream_kernel<f32,2,2> + gap_final_kernel", bound="hbm",
                      achieved=gap_achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                      frac=gap_achieved / HBM_PEAK_GBS, bytes_per_launch=gap_bytes,
                      launch_ms=gap_avg_ms,
-                     traffic=counter_traffic("srot::gap_stream_kernel<0, 2, 2>"))
+                     traffic=counter_traffic("srot::gap_stream_kernel<0, 2, 2, false, false>"))
 
     cpu = None
     if not args.no_cpu:
@@ -236,8 +236,9 @@ def main():
 def bench_sweep(args):
     """The per-pass gap sweep on a cost larger than the 256 MB Infinity Cache:
     m = n = 16384 mixture points, FP32 stored cost (1 GiB), after one pass of
-    block steps from the initial plan; kernel time from HIP events around
-    srot_gap_async on the solver's stream."""
+    block steps from the initial plan; sweep plus final-sum kernel time from
+    HIP events around srot_gap_async on the solver's stream (a device
+    destination: no copy)."""
     import torch
     from paper_2103_05857_amd import inputs as I
     from paper_2103_05857_amd import srot as S
@@ -301,10 +302,11 @@ def bench_sweep(args):
     fw.close()
     fw_bytes = 4.0 * n * n + 24.0 * fw_nnz + 8.0 * (3 * n + 4 * n)
     return {"workload": f"gap sweep, m=n={n} FP32 stored cost (1 GiB), after one pass",
-            "kernel": "gap_stream_kernel<f32,2,2> (+ 40-byte readback copy)", "bound": "hbm",
+            "kernel": "gap_stream_kernel<f32,4,1,rotated> + gap_final_kernel", "bound": "hbm",
             "us": t * 1e6, "bytes": byts, "achieved": byts / t / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": byts / t / 1e9 / HBM_PEAK_GBS,
-            "traffic": counter_traffic("srot::gap_stream_kernel<0, 2, 2>", SWEEP_PROFILE, grid=2048 * 256),
+            "traffic": counter_traffic("srot::gap_stream_kernel<0, 4, 1, false, true>", SWEEP_PROFILE,
+                                       grid=512 * 256),
             "chain_us_per_block_update_first_pass": chain_us,
             "full_fw": {"workload": f"full FW, m=n={n}, FP32 stored cost (1 GiB), w=1, ELS, iterations 4-23",
                         "us_per_iteration": fw_s * 1e6, "bytes_per_iteration": fw_bytes,
@@ -555,7 +557,7 @@ def bench_fused(args):
     chain_flops = 10.0 * n * n
     sweep_flops = 10.0 * n * n
     cc = profile_counters(FUSED_PROFILE, FUSED_SRC, "srot::chain_team_kernel<2, false>")
-    cs = profile_counters(FUSED_PROFILE, FUSED_SRC, "srot::gap_sweep_kernel<2, 1, 2>")
+    cs = profile_counters(FUSED_PROFILE, FUSED_SRC, "srot::gap_sweep_kernel<2, 1, 2")
 
     def valu_share(c):
         if not c or not c.get("SQ_WAVE_CYCLES"):

@@ -143,10 +143,17 @@ int srot_gap_async(srot_handle *h, double *out5);
 
 /* Runs passes of m block steps, measuring the gap every opt->gap_every passes
  * and stopping at the first measurement with g <= opt->eps, or after
- * opt->max_passes passes (Sec. 3.1 stopping rule).
+ * opt->max_passes passes (Sec. 3.1 stopping rule).  The stop test runs on
+ * the device: passes are queued eight at a time and the host synchronises
+ * once per eight; passes queued after the stopping one do nothing, so the
+ * state left is that of the stopping pass (the same as testing after every
+ * pass on the host).
  *   out3    host, {g, f, D} at the last measurement.
  *   passes  host, number of passes run by this call.
- * Returns SROT_OK when converged, SROT_NOT_CONVERGED otherwise. */
+ * Returns SROT_OK when converged, SROT_NOT_CONVERGED otherwise, SROT_EHIP
+ * when a team-chain member (rows of 4097-65536 columns) gave up waiting for
+ * the others (the plan is then inconsistent; the failure stays recorded
+ * until srot_set_state loads a state). */
 int srot_solve(srot_handle *h, double *out3, int64_t *passes);
 
 /* Copies the dense plan T (device, m x n double) and the residual

@@ -95,7 +95,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t T, r, mask, idx, G, j, g, partials, scalars, flags, slow, Y4, adj, ga_w, team, total;
+    size_t T, r, mask, idx, G, j, g, partials, scalars, meas, flags, slow, Y4, adj, ga_w, team, total;
     int64_t idx_cap;
     int32_t gap_blocks;
 };
@@ -132,6 +132,7 @@ Layout make_layout(int64_t m, int64_t n)
     L.partials = off;
     off = align_up(off + sizeof(double) * 8 * (size_t)L.gap_blocks);
     L.scalars = off; off = align_up(off + sizeof(double) * 8);
+    L.meas = off; off = align_up(off + sizeof(double) * 8);
     L.flags = off; off = align_up(off + sizeof(int32_t) * 8);
     L.slow = off; off = align_up(off + 4 * sizeof(int64_t));
     L.Y4 = off; off = align_up(off + 16 * (size_t)srot::y4_entries(n));
@@ -177,15 +178,17 @@ int draw_indices(srot_handle *h, int64_t k, int64_t *count, const int32_t **out)
     return SROT_OK;
 }
 
-int run_steps(srot_handle *h, int64_t nsteps, int32_t *trace_j, double *trace_gamma)
+int run_steps(srot_handle *h, int64_t nsteps, int32_t *trace_j, double *trace_gamma,
+              const srot::ProblemView *Pv = nullptr)
 {
+    const srot::ProblemView &P = Pv ? *Pv : h->P;
     int64_t done = 0;
     while (done < nsteps) {
         int64_t cnt = nsteps - done;
         const int32_t *idx = nullptr;
         int rc = draw_indices(h, h->k, &cnt, &idx);
         if (rc != SROT_OK) return rc;
-        SROT_HIP(srot::launch_chain(h->P, h->S, idx, h->k, cnt, h->opt.step_rule,
+        SROT_HIP(srot::launch_chain(P, h->S, idx, h->k, cnt, h->opt.step_rule,
                                     trace_j ? trace_j + done : nullptr,
                                     trace_gamma ? trace_gamma + done : nullptr, h->stream));
         h->k += cnt;
@@ -195,15 +198,16 @@ int run_steps(srot_handle *h, int64_t nsteps, int32_t *trace_j, double *trace_ga
 }
 
 int run_variant_steps(srot_handle *h, int pairwise, int64_t nsteps, int32_t *trace_j, int32_t *trace_away,
-                      double *trace_gamma)
+                      double *trace_gamma, const srot::ProblemView *Pv = nullptr)
 {
+    const srot::ProblemView &P = Pv ? *Pv : h->P;
     int64_t done = 0;
     while (done < nsteps) {
         int64_t cnt = nsteps - done;
         const int32_t *idx = nullptr;
         int rc = draw_indices(h, h->k, &cnt, &idx);
         if (rc != SROT_OK) return rc;
-        SROT_HIP(srot::launch_active_steps(h->P, h->S, pairwise, idx, cnt, trace_j ? trace_j + done : nullptr,
+        SROT_HIP(srot::launch_active_steps(P, h->S, pairwise, idx, cnt, trace_j ? trace_j + done : nullptr,
                                            trace_away ? trace_away + done : nullptr,
                                            trace_gamma ? trace_gamma + done : nullptr, h->stream));
         h->k += cnt;
@@ -250,6 +254,63 @@ int measure_gap(srot_handle *h, double *out3)
 }
 
 }  // namespace
+
+// Passes are queued in batches of kSolveBatch.  The final sum of each
+// measuring sweep takes the stop test on the device; once g <= eps every
+// later kernel of the batch returns at its start, so the host reads the
+// stop word once per batch and the state is that of the stopping pass.
+// steps(p, Ps) queues pass p's block steps, after(p, Ps, measured) what
+// follows the pass's sweep (the gap-adaptive sampler's global update).
+constexpr int64_t kSolveBatch = 8;
+
+template <class Steps, class After>
+int solve_on_device(srot_handle *h, double *out3, int64_t *passes, Steps steps, After after)
+{
+    *passes = 0;
+    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
+    const int64_t m = h->P.m, maxp = h->opt.max_passes;
+    int32_t *stop_w = h->S.flags + 4;  // [0] stopped, [1] its pass (low 32 bits)
+    srot::ProblemView Ps = h->P;
+    Ps.stop = stop_w;
+    SROT_HIP(hipMemsetAsync(stop_w, 0, 2 * sizeof(int32_t), h->stream));
+    const int64_t k0 = h->k;
+    bool measured_any = false;
+    for (int64_t p0 = 0; p0 < maxp; p0 += kSolveBatch) {
+        const int64_t p1 = std::min(maxp, p0 + kSolveBatch);
+        for (int64_t p = p0; p < p1; ++p) {
+            int rc = steps(p, Ps);
+            if (rc != SROT_OK) return rc;
+            const bool measure = (p + 1) % h->opt.gap_every == 0 || p + 1 == maxp;
+            if (measure) {
+                SROT_HIP(srot::launch_gap_stop(Ps, h->S, h->stream, stop_w, h->opt.eps, (int32_t)(uint32_t)p));
+                measured_any = true;
+            }
+            rc = after(p, Ps, measure);
+            if (rc != SROT_OK) return rc;
+        }
+        int32_t sw[2] = {0, 0};
+        double host[3];
+        int32_t team_err = 0;
+        SROT_HIP(hipMemcpyAsync(sw, stop_w, sizeof(sw), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipMemcpyAsync(host, h->S.meas, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+        if (h->S.team)
+            SROT_HIP(hipMemcpyAsync(&team_err, h->S.flags + 6, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipStreamSynchronize(h->stream));
+        if (team_err)
+            return fail(SROT_EHIP, "team chain: a member waited too long for the others' records; "
+                                   "the plan and residual are inconsistent");
+        if (measured_any) { out3[0] = host[0]; out3[1] = host[1]; out3[2] = host[2]; }
+        if (sw[0]) {
+            // the batch holds fewer than 2^32 passes: the low bits name the pass
+            const int64_t p = p0 + (int64_t)(uint32_t)((uint32_t)sw[1] - (uint32_t)p0);
+            *passes = p + 1;
+            h->k = k0 + (p + 1) * m;  // the passes queued after it did nothing
+            return SROT_OK;
+        }
+        *passes = p1;
+    }
+    return SROT_NOT_CONVERGED;
+}
 
 extern "C" {
 
@@ -325,6 +386,7 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     h->S.partials = (double *)(base + L.partials);
     h->S.gap_blocks = L.gap_blocks;
     h->S.scalars = (double *)(base + L.scalars);
+    h->S.meas = (double *)(base + L.meas);
     h->S.flags = (int32_t *)(base + L.flags);
     h->S.slow_steps = (int64_t *)(base + L.slow);
     h->S.adj_part = (double *)(base + L.adj);
@@ -433,20 +495,10 @@ int srot_gap_async(srot_handle *h, double *out5)
 int srot_solve(srot_handle *h, double *out3, int64_t *passes)
 {
     if (!h || !out3 || !passes) return fail(SROT_EINVAL, "srot_solve: NULL argument");
-    *passes = 0;
-    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
     const int64_t m = h->P.m;
-    for (int64_t p = 0; p < h->opt.max_passes; ++p) {
-        int rc = run_steps(h, m, nullptr, nullptr);
-        if (rc != SROT_OK) return rc;
-        *passes = p + 1;
-        if ((p + 1) % h->opt.gap_every == 0 || p + 1 == h->opt.max_passes) {
-            rc = measure_gap(h, out3);
-            if (rc != SROT_OK) return rc;
-            if (out3[0] <= h->opt.eps) return SROT_OK;
-        }
-    }
-    return SROT_NOT_CONVERGED;
+    return solve_on_device(
+        h, out3, passes, [&](int64_t, const srot::ProblemView &Ps) { return run_steps(h, m, nullptr, nullptr, &Ps); },
+        [](int64_t, const srot::ProblemView &, bool) { return (int)SROT_OK; });
 }
 
 int srot_get_plan(srot_handle *h, double *T_out, double *r_out)
@@ -486,6 +538,8 @@ int srot_set_state(srot_handle *h, const double *T_in, const double *r_in, int64
     else
         SROT_HIP(srot::launch_residual(h->P, h->S, h->stream));
     SROT_HIP(srot::launch_mask_build(h->P, h->S, h->stream));
+    // a consistent state again: a team-chain failure recorded before is over
+    SROT_HIP(hipMemsetAsync(h->S.flags + 6, 0, sizeof(int32_t), h->stream));
     h->k = k;
     return SROT_OK;
 }
@@ -620,20 +674,14 @@ int srot_solve_variant(srot_handle *h, int variant, double *out3, int64_t *passe
     int rc = variant_ok(h, variant, "srot_solve_variant");
     if (rc != SROT_OK) return rc;
     if (!out3 || !passes) return fail(SROT_EINVAL, "srot_solve_variant: NULL argument");
-    *passes = 0;
-    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
     const int64_t m = h->P.m;
-    for (int64_t p = 0; p < h->opt.max_passes; ++p) {
-        rc = run_variant_steps(h, variant == SROT_STEP_PAIRWISE, m, nullptr, nullptr, nullptr);
-        if (rc != SROT_OK) return rc;
-        *passes = p + 1;
-        if ((p + 1) % h->opt.gap_every == 0 || p + 1 == h->opt.max_passes) {
-            rc = measure_gap(h, out3);
-            if (rc != SROT_OK) return rc;
-            if (out3[0] <= h->opt.eps) return SROT_OK;
-        }
-    }
-    return SROT_NOT_CONVERGED;
+    const int pairwise = variant == SROT_STEP_PAIRWISE;
+    return solve_on_device(
+        h, out3, passes,
+        [&](int64_t, const srot::ProblemView &Ps) {
+            return run_variant_steps(h, pairwise, m, nullptr, nullptr, nullptr, &Ps);
+        },
+        [](int64_t, const srot::ProblemView &, bool) { return (int)SROT_OK; });
 }
 
 int srot_ga_reset(srot_handle *h, double init)
@@ -683,27 +731,23 @@ int srot_solve_ga(srot_handle *h, double init, int64_t period, double *out3, int
     if (period < 1) return fail(SROT_EINVAL, "srot_solve_ga: period must be >= 1");
     rc = srot_ga_reset(h, init > 0.0 ? init : SROT_GA_INIT);
     if (rc != SROT_OK) return rc;
-    *passes = 0;
-    out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
     const int64_t m = h->P.m;
-    for (int64_t p = 0; p < h->opt.max_passes; ++p) {
-        SROT_HIP(srot::launch_ga_steps(h->P, h->S, nullptr, h->opt.seed, h->k, m, h->opt.step_rule, nullptr,
-                                       nullptr, nullptr, nullptr, h->stream));
-        h->k += m;
-        *passes = p + 1;
-        bool swept = false;
-        if ((p + 1) % h->opt.gap_every == 0 || p + 1 == h->opt.max_passes) {
-            rc = measure_gap(h, out3);
-            if (rc != SROT_OK) return rc;
-            if (out3[0] <= h->opt.eps) return SROT_OK;
-            swept = true;
-        }
-        if ((p + 1) % period == 0) {
-            if (!swept) SROT_HIP(srot::launch_gap(h->P, h->S, h->stream));
-            SROT_HIP(srot::launch_ga_fill(h->P, h->S, h->S.row_g, 0.0, h->stream));
-        }
-    }
-    return SROT_NOT_CONVERGED;
+    return solve_on_device(
+        h, out3, passes,
+        [&](int64_t, const srot::ProblemView &Ps) {
+            SROT_HIP(srot::launch_ga_steps(Ps, h->S, nullptr, h->opt.seed, h->k, m, h->opt.step_rule, nullptr,
+                                           nullptr, nullptr, nullptr, h->stream));
+            h->k += m;
+            return (int)SROT_OK;
+        },
+        [&](int64_t p, const srot::ProblemView &Ps, bool swept) {
+            // global update of the stored block gaps from a sweep (Alg. A.4)
+            if ((p + 1) % period == 0) {
+                if (!swept) SROT_HIP(srot::launch_gap(Ps, h->S, h->stream));
+                SROT_HIP(srot::launch_ga_fill(Ps, h->S, h->S.row_g, 0.0, h->stream));
+            }
+            return (int)SROT_OK;
+        });
 }
 
 int srot_barycentric(srot_handle *h, float *Xhat)

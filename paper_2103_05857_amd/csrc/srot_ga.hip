@@ -50,6 +50,7 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
                                                      int32_t *__restrict__ tr_i, int32_t *__restrict__ tr_j,
                                                      double *__restrict__ tr_gamma, double *__restrict__ tr_g)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NW = NT / 64;
@@ -237,9 +238,12 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
     }
 }
 
-// W_i <- max(g_i, 0) from the gap sweep (global update), or W_i <- value.
-__global__ void ga_fill_kernel(int32_t m, const double *__restrict__ src, double value, double *__restrict__ W)
+// W_i <- max(g_i, 0) from the gap sweep (global update), or W_i <- value;
+// nothing once a solve has stopped (stop set).
+__global__ void ga_fill_kernel(int32_t m, const double *__restrict__ src, double value, double *__restrict__ W,
+                               const int32_t *__restrict__ stop)
 {
+    if (stop && *stop) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
         W[i] = src ? fmax(src[i], 0.0) : value;
 }
@@ -303,7 +307,7 @@ hipError_t launch_ga_fill(const ProblemView &P, const DeviceState &S, const doub
                           hipStream_t stream)
 {
     const int blocks = (int)std::min<int64_t>((P.m + 255) / 256, 1024);
-    hipLaunchKernelGGL(ga_fill_kernel, dim3(blocks), dim3(256), 0, stream, P.m, src, value, S.ga_w);
+    hipLaunchKernelGGL(ga_fill_kernel, dim3(blocks), dim3(256), 0, stream, P.m, src, value, S.ga_w, P.stop);
     return hipGetLastError();
 }
 

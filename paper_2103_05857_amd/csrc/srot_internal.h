@@ -19,6 +19,10 @@ struct ProblemView {
     const double *a;       // m
     const double *b;       // n
     double w;
+    // When set, a device word: block-step and gap-sweep kernels return at
+    // once while it is nonzero (set by the final sum of a sweep that found
+    // g <= eps, so passes queued after it do nothing).
+    const int32_t *stop = nullptr;
 };
 
 // Column ownership shared by the step and gap kernels of one handle: thread
@@ -50,7 +54,9 @@ struct DeviceState {
     double *partials;      // gap_blocks x 8 (gap sweep), or the FW step-size partials
     int32_t gap_blocks;
     double *scalars;       // 8: g, f, D, ...
-    int32_t *flags;        // 8: [0] validation/index error flags, [4] gap-sweep ticket, [5] FW ticket
+    double *meas;          // 8: {g, f, D, <T,C>, ||r||^2} of a solve's last measuring sweep
+    int32_t *flags;        // 8: [0] validation/index error flags, [1..3] FW run state, [4..5] solve stop word and
+                           // pass, [6] team-chain error
     int64_t *slow_steps;   // 4: slow-path step counts of the last chain launch (diagnostic)
     double *adj_part;      // adjoint_slices_cap(m) x 3 x n per-slice column sums
     unsigned long long *team_rec;  // 2 x TEAM_MAX_MEMBERS x TEAM_REC_STRIDE exchange words of the team chain
@@ -88,6 +94,11 @@ hipError_t launch_chain(const ProblemView &P, const DeviceState &S, const int32_
 // The sweep and its final sums into S.scalars[0..4] (and out_dev[0..4],
 // device memory, when given).
 hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t stream, double *out_dev = nullptr);
+// The same within a solve whose P.stop is stop_w (the sums also into
+// S.meas): g <= eps sets stop_w[0] = 1 and stop_w[1] = pass; nothing runs
+// once stop_w[0] is set.
+hipError_t launch_gap_stop(const ProblemView &P, const DeviceState &S, hipStream_t stream, int32_t *stop_w, double eps,
+                           int32_t pass);
 
 // Screened-LMO chain (srot_screen.hip): stored FP32 cost in the 256 x {8,16}
 // x 4 ownership.  launch_cost_bounds writes {max |c_ij|, max(sum a, max b)}

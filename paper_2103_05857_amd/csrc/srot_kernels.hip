@@ -49,6 +49,7 @@ __global__ __launch_bounds__(NT) void chain_kernel(ProblemView P, double *__rest
                                                    double *__restrict__ trace_gamma,
                                                    int64_t *__restrict__ slow_steps)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     const int64_t slow = chain_run<NT, CPT, VEC, COST, TRACE>(P, T, rg, M, idx, k0, nsteps, rule,
                                                              trace_j, trace_gamma);
     if (threadIdx.x == 0) {
@@ -74,6 +75,7 @@ __global__ __launch_bounds__(GLB_NT) void chain_glb_kernel(ProblemView P, double
                                                            double *__restrict__ trace_gamma,
                                                            int64_t *__restrict__ stats)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NT = GLB_NT, NW = NT / 64;
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(WIDE_NT) void chain_wide_kernel(ProblemView P, doub
                                                              double *__restrict__ trace_gamma,
                                                              double delta2, int64_t *__restrict__ stats)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     constexpr int NW = WIDE_NT / 64;
     if (threadIdx.x == 0) stats[2] = SROT_CHAIN_WIDE;
     extern __shared__ float r32[];
@@ -569,11 +572,19 @@ __device__ __forceinline__ void gap_partials(const ProblemView &P, const double 
     }
 }
 
+// The final sums of a sweep; in a solve (stop_w set) also the stop test of
+// Sec. 3.1: g <= eps sets stop_w[0] and records the pass in stop_w[1].
 __global__ __launch_bounds__(GAP_FINAL_NT) void gap_final_kernel(ProblemView P, const double *__restrict__ partials,
                                                                  int nb, double *__restrict__ out,
-                                                                 double *__restrict__ out2)
+                                                                 double *__restrict__ out2, int32_t *__restrict__ stop_w,
+                                                                 double eps, int32_t pass)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped: the last sums stay
     gap_total(P.w, partials, nb, out, out2);
+    if (stop_w && threadIdx.x == 0 && out[0] <= eps) {
+        stop_w[1] = pass;
+        stop_w[0] = 1;
+    }
 }
 
 template <int COST, int VEC, int R, bool FW>
@@ -586,6 +597,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double
                                                            double *__restrict__ partials,
                                                            double *__restrict__ out, FwSweep fw)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int GU = 16 / VEC;  // vectors per lane per group: 16 columns
@@ -811,6 +823,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
                                                             double *__restrict__ partials,
                                                             double *__restrict__ out, FwSweep fw)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr int VEC = 16 / (int)sizeof(CT);  // columns per 16-byte vector
     constexpr int RV = VEC / 2;                // 16-byte vectors of r per cost vector
@@ -1523,7 +1536,18 @@ hipError_t launch_gap(const ProblemView &P, const DeviceState &S, hipStream_t st
     hipError_t e = launch_gap_any(P, S, nullptr, stream, &nb);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(GAP_FINAL_NT), 0, stream, P, (const double *)S.partials, nb,
-                       S.scalars, out_dev);
+                       S.scalars, out_dev, (int32_t *)nullptr, 0.0, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gap_stop(const ProblemView &P, const DeviceState &S, hipStream_t stream, int32_t *stop_w, double eps,
+                           int32_t pass)
+{
+    int nb = 0;
+    hipError_t e = launch_gap_any(P, S, nullptr, stream, &nb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(GAP_FINAL_NT), 0, stream, P, (const double *)S.partials, nb,
+                       S.scalars, S.meas, stop_w, eps, pass);
     return hipGetLastError();
 }
 

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                                                                double *__restrict__ trace_gamma,
                                                                int64_t *__restrict__ slow_steps, double err_c)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     static_assert(CPT == 4 || CPT == 8 || CPT == 16, "4 owner threads x CPT columns per lane");
     constexpr int NC = 256 * CPT;   // columns of the ownership (n <= NC)
     constexpr int G = CPT / 4;      // 16-byte groups per owner thread

@@ -37,7 +37,7 @@
 // step s + 1, which each member publishes only after reading step s.  Every wait is
 // bounded: after TEAM_SPIN_LIMIT polls, or once another member has given up,
 // a member raises the team error flag and stops (the plan is then left
-// inconsistent and the caller reports the failure).
+// inconsistent and the caller reports the failure; the flag stays set).
 // ---------------------------------------------------------------------------
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -257,6 +257,7 @@ __global__ __launch_bounds__(TEAM_BLOCK) void chain_team_kernel(ProblemView P, d
                                                                 int32_t *__restrict__ err,
                                                                 int64_t *__restrict__ stats)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F64, double, float>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     __shared__ Part s_part[2][TEAM_NW];
@@ -482,14 +483,15 @@ __global__ __launch_bounds__(TEAM_BLOCK) void chain_team_kernel(ProblemView P, d
     if (w_id == 0 && tid == 0) stats[2] = SROT_CHAIN_TEAM;
 }
 
-// Zeroes the exchange records and the team error flag before a launch, so
-// that tags (the step number within the launch, from 1) never match a
-// record of an earlier launch.  A kernel rather than a memset, so that the
-// launch sequence can be captured in a graph.
-__global__ void team_clear_kernel(unsigned long long *__restrict__ rec, int words, int32_t *__restrict__ err)
+// Zeroes the exchange records before a launch, so that tags (the step
+// number within the launch, from 1) never match a record of an earlier
+// launch.  A kernel rather than a memset, so that the launch sequence can
+// be captured in a graph.  The team error flag is not cleared here: once
+// set it stays set (later launches stop at their first wait) until the
+// handle's state is rewritten (srot_set_state) or the handle is made again.
+__global__ void team_clear_kernel(unsigned long long *__restrict__ rec, int words)
 {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < words; k += gridDim.x * blockDim.x) rec[k] = 0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
 }
 
 }  // namespace
@@ -509,7 +511,7 @@ static hipError_t launch_team_cost(const ProblemView &P, const DeviceState &S, c
 {
     const int nwg = team_members(P.n);
     const int words = 2 * TEAM_MAX_MEMBERS * TEAM_REC_STRIDE;
-    hipLaunchKernelGGL(team_clear_kernel, dim3(8), dim3(256), 0, st, S.team_rec, words, S.flags + 6);
+    hipLaunchKernelGGL(team_clear_kernel, dim3(8), dim3(256), 0, st, S.team_rec, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tj || tg)

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
                                                          int32_t *__restrict__ trace_away,
                                                          double *__restrict__ trace_gamma)
 {
+    if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
     constexpr int NW = NT / 64;

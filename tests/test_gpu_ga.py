@@ -196,6 +196,41 @@ def test_solve_ga_matches_the_oracle_outer_iterations(period):
     assert abs(f - hist[-1]["f"]) <= g + hist[-1]["g"] + 1e-15     # both within their gaps of f*
 
 
+@pytest.mark.parametrize("period,gap_every,max_passes", [(1, 1, 2000), (4, 1, 2000), (3, 2, 2000), (2, 1, 9)])
+def test_solve_ga_leaves_the_state_of_its_stopping_pass(period, gap_every, max_passes):
+    """The stop test runs on the device with passes queued ahead: plan,
+    residual and stored row gaps left are those of the stopping pass, the
+    same as inner iterations and global updates taken by hand (no update at
+    the stopping pass), and (g, f, D) is the sweep of that state."""
+    S = _S()
+    m, n = 40, 50
+    d = I.problem_mixture(35, m, n, cost_dtype=np.float64)
+    opts = dict(eps=1e-6, max_passes=max_passes, gap_every=gap_every, seed=2)
+    sol, _ = _pair(d, "stored", 1.0, **opts)
+    ref, _ = _pair(d, "stored", 1.0, **opts)
+    st, (g, f, D), passes = S.srot_solve_ga(sol.h, 0.0, period)
+    S.srot_ga_reset(ref.h)
+    for p in range(passes):
+        S.srot_step_ga(ref.h, m)
+        if (p + 1) % period == 0 and not (st == S.SROT_OK and p + 1 == passes):
+            S.srot_ga_refresh(ref.h)
+    T1, r1 = sol.plan()
+    T2, r2 = ref.plan()
+    assert torch.equal(T1, T2) and torch.equal(r1, r2)
+    W1 = torch.empty(m, dtype=torch.float64, device="cuda")
+    W2 = torch.empty(m, dtype=torch.float64, device="cuda")
+    S.srot_ga_weights(sol.h, W1)
+    S.srot_ga_weights(ref.h, W2)
+    assert torch.equal(W1, W2)
+    assert (g, f, D) == tuple(ref.gap())
+    if st == S.SROT_OK:
+        assert g <= 1e-6 and passes % gap_every == 0
+    else:
+        assert passes == max_passes
+    sol.close()
+    ref.close()
+
+
 def test_ga_argument_checks():
     S = _S()
     d = I.problem_mixture(36, 10, 12, cost_dtype=np.float64)

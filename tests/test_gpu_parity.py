@@ -229,6 +229,40 @@ def test_solve_stops_at_same_pass_as_oracle():
     assert g <= 1e-6
 
 
+@pytest.mark.parametrize("m,n,gap_every,max_passes", [(200, 300, 1, 400), (150, 256, 3, 400),
+                                                       (96, 5000, 1, 400), (120, 700, 2, 13)])
+def test_solve_leaves_the_state_of_its_stopping_pass(m, n, gap_every, max_passes):
+    """The stop test runs on the device with passes queued ahead: the plan,
+    residual and step counter left are those of the stopping pass (the same
+    as stepping that many passes by hand), the reported (g, f, D) is the
+    sweep of that state, and stepping on continues the same index stream.
+    Covers gap_every > 1, a pass budget that ends mid-batch (13) and the
+    team chain (5000 columns)."""
+    _need_gpu()
+    d = I.problem_mixture(5, m, n)
+    opts = dict(seed=6, eps=1e-6, max_passes=max_passes, gap_every=gap_every)
+    sol = _gpu_problem(d, "stored", 1.0, **opts)
+    status, (g, f, D), passes = sol.solve()
+    ref = _gpu_problem(d, "stored", 1.0, **opts)
+    for _ in range(passes):
+        ref.step(m)  # one launch per pass, as the solve (launch boundaries shape the chain's prefetch)
+    T1, r1 = sol.plan()
+    T2, r2 = ref.plan()
+    assert torch.equal(T1, T2) and torch.equal(r1, r2)
+    assert (g, f, D) == tuple(ref.gap())
+    if status == _S().SROT_OK:
+        assert g <= 1e-6 and passes % gap_every == 0
+    else:
+        assert passes == max_passes and g > 1e-6
+    sol.step(m)
+    ref.step(m)
+    T1, _ = sol.plan()
+    T2, _ = ref.plan()
+    assert torch.equal(T1, T2)
+    sol.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("cost_mode,dtype", [("stored", np.float32), ("stored", np.float64),
                                              ("sqeuclid", np.float32)])
 def test_gap_sweep_on_given_plans(cost_mode, dtype):

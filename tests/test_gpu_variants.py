@@ -204,6 +204,32 @@ def test_variants_converge_to_the_optimum(variant):
     assert abs(f - ref["f"]) <= g + ref["g"] + 1e-15       # both within their gaps of f*
 
 
+@pytest.mark.parametrize("variant,gap_every,max_passes", [(1, 1, 400), (2, 2, 400), (1, 1, 11)])
+def test_solve_variant_leaves_the_state_of_its_stopping_pass(variant, gap_every, max_passes):
+    """The stop test runs on the device with passes queued ahead: the plan
+    and residual left are those of the stopping pass (as stepping that many
+    passes by hand) and (g, f, D) is the sweep of that state."""
+    S = _S()
+    m, n = 60, 90
+    d = I.problem_mixture(16, m, n, cost_dtype=np.float64)
+    opts = dict(eps=1e-7, max_passes=max_passes, gap_every=gap_every, seed=3)
+    sol, _ = _pair(d, "stored", 1.0, **opts)
+    ref, _ = _pair(d, "stored", 1.0, **opts)
+    st, (g, f, D), passes = S.srot_solve_variant(sol.h, variant)
+    for _ in range(passes):
+        S.srot_step_variant(ref.h, variant, m)  # one launch per pass, as the solve
+    T1, r1 = sol.plan()
+    T2, r2 = ref.plan()
+    assert torch.equal(T1, T2) and torch.equal(r1, r2)
+    assert (g, f, D) == tuple(ref.gap())
+    if st == S.SROT_OK:
+        assert g <= 1e-7 and passes % gap_every == 0
+    else:
+        assert passes == max_passes
+    sol.close()
+    ref.close()
+
+
 def test_variant_argument_checks():
     S = _S()
     d = I.problem_mixture(16, 10, 12, cost_dtype=np.float64)
