@@ -595,12 +595,12 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double
                                                            int32_t *__restrict__ row_j,
                                                            double *__restrict__ row_g,
                                                            double *__restrict__ partials,
-                                                           double *__restrict__ out, FwSweep fw)
+                                                           double *__restrict__ out, FwSweep fw, double delta2)
 {
     if (P.stop && *P.stop) return;  // the solve has stopped
     using CT = typename std::conditional<COST == SROT_COST_F32, float, double>::type;
     constexpr bool FUSED = (COST == SROT_COST_SQEUCLID);
-    constexpr int GU = 16 / VEC;  // vectors per lane per group: 16 columns
+    constexpr int GU = (FUSED && R > 2) ? 8 : 16 / VEC;  // vectors per lane per group
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int m = P.m, n = P.n;
     const double w = P.w;
@@ -684,58 +684,116 @@ __global__ __launch_bounds__(GAP_NT) void gap_sweep_kernel(ProblemView P, double
         int bj[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) { best[k] = INFINITY; bj[k] = 0x7fffffff; }
-        for (int q0 = 0; q0 < nq; q0 += GU) {
-            CT cv[R][GU][VEC];
-            if constexpr (!FUSED) {
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const CT *__restrict__ crow = C + (size_t)ir[k] * (size_t)n;
-#pragma unroll
-                    for (int u = 0; u < GU; ++u) {
-                        const int jb = ((q0 + u) * 64 + lane) * VEC;
-                        const int jc = jb < n ? jb : 0;
-                        if constexpr (VEC == 4) {
-                            const float4 v = *reinterpret_cast<const float4 *>(crow + jc);
-                            cv[k][u][0] = v.x; cv[k][u][1] = v.y; cv[k][u][2] = v.z; cv[k][u][3] = v.w;
-                        } else if constexpr (VEC == 2) {
-                            const double2 v = *reinterpret_cast<const double2 *>(crow + jc);
-                            cv[k][u][0] = v.x; cv[k][u][1] = v.y;
-                        } else {
-                            cv[k][u][0] = crow[jc];
+        auto plain_scan = [&]() {
+            for (int q0 = 0; q0 < nq; q0 += GU) {
+                CT cv[R][GU][VEC];
+                if constexpr (!FUSED) {
+    #pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const CT *__restrict__ crow = C + (size_t)ir[k] * (size_t)n;
+    #pragma unroll
+                        for (int u = 0; u < GU; ++u) {
+                            const int jb = ((q0 + u) * 64 + lane) * VEC;
+                            const int jc = jb < n ? jb : 0;
+                            if constexpr (VEC == 4) {
+                                const float4 v = *reinterpret_cast<const float4 *>(crow + jc);
+                                cv[k][u][0] = v.x; cv[k][u][1] = v.y; cv[k][u][2] = v.z; cv[k][u][3] = v.w;
+                            } else if constexpr (VEC == 2) {
+                                const double2 v = *reinterpret_cast<const double2 *>(crow + jc);
+                                cv[k][u][0] = v.x; cv[k][u][1] = v.y;
+                            } else {
+                                cv[k][u][0] = crow[jc];
+                            }
+                        }
+                    }
+                }
+    #pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const int jb = ((q0 + u) * 64 + lane) * VEC;
+                    if (jb >= n) continue;
+                    double rv[VEC];
+                    if constexpr (VEC == 4) {
+                        const double2 ra = *reinterpret_cast<const double2 *>(rg + jb);
+                        const double2 rb = *reinterpret_cast<const double2 *>(rg + jb + 2);
+                        rv[0] = ra.x; rv[1] = ra.y; rv[2] = rb.x; rv[3] = rb.y;
+                    } else if constexpr (VEC == 2) {
+                        const double2 ra = *reinterpret_cast<const double2 *>(rg + jb);
+                        rv[0] = ra.x; rv[1] = ra.y;
+                    } else {
+                        rv[0] = rg[jb];
+                    }
+                    float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if constexpr (FUSED) y = P.Y4[jb];
+    #pragma unroll
+                    for (int k = 0; k < R; ++k) {
+    #pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            double c;
+                            if constexpr (FUSED) c = sqdist(xr[k][0], xr[k][1], xr[k][2], y.x, y.y, y.z);
+                            else c = (double)cv[k][u][e];
+                            const double v = c + w * rv[e];
+                            if (v < best[k]) { best[k] = v; bj[k] = jb + e; }
                         }
                     }
                 }
             }
+        };
+        bool scanned = false;
+        if constexpr (FUSED) {
+            if (delta2 > 0.0) {
+                // FP32 screen (the bound of the wide-row chain: every
+                // |v'_j - v_j| <= delta2 / 2): a column is evaluated exactly
+                // when its screen value is within delta2 of the smallest
+                // screen value met so far by the wave, a set that holds every
+                // exact minimiser (its screen value is within delta2 of every
+                // other column's); lanes meet their columns in increasing
+                // order, so '<' keeps the lowest index.
+                const float w32 = (float)w;
+                float bw[R];
 #pragma unroll
-            for (int u = 0; u < GU; ++u) {
-                const int jb = ((q0 + u) * 64 + lane) * VEC;
-                if (jb >= n) continue;
-                double rv[VEC];
-                if constexpr (VEC == 4) {
-                    const double2 ra = *reinterpret_cast<const double2 *>(rg + jb);
-                    const double2 rb = *reinterpret_cast<const double2 *>(rg + jb + 2);
-                    rv[0] = ra.x; rv[1] = ra.y; rv[2] = rb.x; rv[3] = rb.y;
-                } else if constexpr (VEC == 2) {
-                    const double2 ra = *reinterpret_cast<const double2 *>(rg + jb);
-                    rv[0] = ra.x; rv[1] = ra.y;
-                } else {
-                    rv[0] = rg[jb];
-                }
-                float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
-                if constexpr (FUSED) y = P.Y4[jb];
+                for (int k = 0; k < R; ++k) bw[k] = INFINITY;
+                for (int q0 = 0; q0 < nq; q0 += GU) {
+                    double rvv[GU];
+                    float4 yy[GU];
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
+                    for (int u = 0; u < GU; ++u) {
+                        const int jb = (q0 + u) * 64 + lane;
+                        const int jc = jb < n ? jb : 0;
+                        rvv[u] = rg[jc];
+                        yy[u] = P.Y4[jc];
+                    }
+                    float vp[R][GU];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        double c;
-                        if constexpr (FUSED) c = sqdist(xr[k][0], xr[k][1], xr[k][2], y.x, y.y, y.z);
-                        else c = (double)cv[k][u][e];
-                        const double v = c + w * rv[e];
-                        if (v < best[k]) { best[k] = v; bj[k] = jb + e; }
+                    for (int k = 0; k < R; ++k) {
+                        float bl = bw[k];
+#pragma unroll
+                        for (int u = 0; u < GU; ++u) {
+                            const float d0 = xr[k][0] - yy[u].x, d1 = xr[k][1] - yy[u].y, d2 = xr[k][2] - yy[u].z;
+                            const float c = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+                            const float v = fmaf(w32, (float)rvv[u], c);
+                            vp[k][u] = ((q0 + u) * 64 + lane < n) ? v : INFINITY;
+                            bl = fminf(bl, vp[k][u]);
+                        }
+                        bw[k] = wave_min_f32(bl);
+                    }
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const float thr = __double2float_ru((double)bw[k] + delta2);
+#pragma unroll
+                        for (int u = 0; u < GU; ++u) {
+                            if (vp[k][u] <= thr) {
+                                const int jb = (q0 + u) * 64 + lane;
+                                const double v = sqdist(xr[k][0], xr[k][1], xr[k][2], yy[u].x, yy[u].y, yy[u].z) +
+                                                 w * rvv[u];
+                                if (v < best[k]) { best[k] = v; bj[k] = jb; }
+                            }
+                        }
                     }
                 }
+                scanned = true;
             }
         }
+        if (!scanned) plain_scan();
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             if (i0 + k >= m) break;  // uniform over the wave
@@ -1460,21 +1518,24 @@ int32_t gap_blocks_for(int64_t m)
 }
 
 // Row-strided sweep (fused cost, or rows not split into 16-byte vectors):
-// at most 1024 workgroups, where it measured best.
+// at most 1024 workgroups, where it measured best; each r_j (and target
+// point) read serves R rows: 2, or 4 for the fused cost, whose FP32 screen
+// leaves the loads of r and the points as the larger part of the work.
 template <int COST, int VEC>
 static hipError_t launch_gap_rows(const ProblemView &P, const DeviceState &S, const FwSweep *fw, hipStream_t st,
                                   int *nb_out)
 {
-    constexpr int R = 2;  // each r_j read serves both rows
+    constexpr int R = (COST == SROT_COST_SQEUCLID) ? 4 : 2;
     const int64_t waves = (P.m + R - 1) / R;
     const int nb = (int)std::min<int64_t>(std::min<int64_t>((waves + GAP_NW - 1) / GAP_NW, 1024), S.gap_blocks);
     *nb_out = nb;
     if (fw)
         hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R, true>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r, S.mask,
-                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, *fw);
+                           S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, *fw, S.screen_delta2);
     else
         hipLaunchKernelGGL((gap_sweep_kernel<COST, VEC, R, false>), dim3(nb), dim3(GAP_NT), 0, st, P, S.T, S.r,
-                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, FwSweep{});
+                           S.mask, S.own, S.row_G, S.row_j, S.row_g, S.partials, S.scalars, FwSweep{},
+                           S.screen_delta2);
     return hipGetLastError();
 }
 

@@ -319,6 +319,38 @@ def test_gap_sweep_exact_ties_take_the_lowest_column(n):
     sol.close()
 
 
+@pytest.mark.parametrize("n", [3000, 6000, 20000])
+def test_fused_gap_sweep_exact_ties_take_the_lowest_column(n):
+    """Fused cost: each row's own point copied into three target columns
+    far apart (cost exactly 0 there, r equal: no plan mass, uniform b), so
+    the row minimum is attained exactly three times; the sweep reports the
+    lowest of them, also through the FP32 screen of rows wider than 4096
+    columns."""
+    _need_gpu()
+    m = 7
+    rng = np.random.default_rng(12)
+    X = rng.random((m, 3)).astype(np.float32)
+    Y = rng.random((n, 3)).astype(np.float32)
+    ties = np.stack([np.arange(m) + 100, np.arange(m) + n // 2 + 5, n - 30 - np.arange(m)], axis=1)
+    for i in range(m):
+        Y[ties[i]] = X[i]
+    a = np.full(m, 1.0 / m)
+    b = np.full(n, 1.0 / n)
+    T = np.zeros((m, n))
+    T[np.arange(m), (np.arange(m) * 37 + 1000) % n] = a  # away from the tied columns
+    d = {"a": a, "b": b, "X": X, "Y": Y}
+    P = _oracle_problem(d, "sqeuclid", 1.0)
+    ref = O.gap(P, T)
+    np.testing.assert_array_equal(ref["jstar"], ties[:, 0])
+    sol = _gpu_problem(d, "sqeuclid", 1.0)
+    sol.set_state(torch.from_numpy(T).to(DEV), 0)
+    (g, f, D), rg, rj = sol.gap(per_row=True)
+    np.testing.assert_array_equal(rj.cpu().numpy(), ties[:, 0])
+    np.testing.assert_allclose(rg.cpu().numpy(), ref["grow"], rtol=1e-9, atol=1e-15)
+    _close_fg((g, f, D), ref)
+    sol.close()
+
+
 def test_gap_async_into_device_and_pinned_memory():
     """srot_gap_async: the final-sum kernel writes a device destination
     itself, a pinned host one gets a copy; both equal srot_gap bitwise."""
