@@ -83,7 +83,11 @@ def counter_traffic(kernel_prefix, profile=PROFILE, grid=None):
         return None
     for name, v in blob["per_dispatch"].items():
         if name.startswith(kernel_prefix) and (grid is None or name.endswith(f"[grid {grid}]")):
-            return 1024.0 * (v["fetch_kib"] * blob["fetch_scale"] + v["write_kib"] * blob["write_scale"])
+            fetch = v.get("fetch_kib", v.get("FETCH_SIZE"))
+            write = v.get("write_kib", v.get("WRITE_SIZE"))
+            if fetch is None or write is None:
+                return None
+            return 1024.0 * (fetch * blob["fetch_scale"] + write * blob["write_scale"])
     return None
 
 
