@@ -144,8 +144,10 @@ int srot_gap_async(srot_handle *h, double *out5);
 /* Runs passes of m block steps, measuring the gap every opt->gap_every passes
  * and stopping at the first measurement with g <= opt->eps, or after
  * opt->max_passes passes (Sec. 3.1 stopping rule).  The stop test runs on
- * the device: passes are queued eight at a time and the host synchronises
- * once per eight; passes queued after the stopping one do nothing, so the
+ * the device: passes are queued four at a time, the next four before the
+ * host reads the last ones' stop word (copied to pinned host memory the
+ * handle holds from its first solve), so the GPU does not wait for the
+ * host between them; passes queued after the stopping one do nothing, so the
  * state left is that of the stopping pass (the same as testing after every
  * pass on the host).
  *   out3    host, {g, f, D} at the last measurement.
@@ -339,8 +341,9 @@ int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma);
  * opt->max_passes iterations have run.  out3 (host) = {g, f, D} at the last
  * iterate; *iters (host) = iterations run.  The stop test runs on the
  * device (a sweep that finds the run converged does nothing), so
- * iterations are queued in batches of 8 and the host synchronises once per
- * batch.  Returns SROT_OK or SROT_NOT_CONVERGED. */
+ * iterations are queued in batches of 4, the next batch before the host
+ * reads the last one's run state (as srot_solve).  Returns SROT_OK or
+ * SROT_NOT_CONVERGED. */
 int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters);
 
 /* Barycentric projection of the source points through the plan
@@ -414,7 +417,9 @@ int srot_get_tiles_batched(srot_batch *h, int32_t *tiles, float *ms_per_step);
 
 void srot_destroy_batched(srot_batch *h);
 
-/* Destroys the handle (host memory only; the caller frees its buffers). */
+/* Destroys the handle: its host memory, and the pinned readback words and
+ * events of the solve loops (after the handle's stream has drained); the
+ * caller frees its buffers. */
 void srot_destroy(srot_handle *h);
 
 const char *srot_strerror(int status);

@@ -23,6 +23,14 @@ struct srot_handle {
     int64_t fw_k;  // full Frank-Wolfe iteration counter (decay rule of Alg. A.1)
     void *scratch;            // this device's copy of `scratch` (below), or null
     hipError_t scratch_err;   // why `scratch` is null
+    // What a solve loop reads back per batch, in pinned host memory (two
+    // slots, so the next batch is queued before the last one is read) with
+    // an event per slot; made by srot_init, freed by srot_destroy.
+    struct Readback {
+        int32_t words[4];  // the stop word and its pass and the team error (or the FW run state)
+        double sums[3];    // g, f, D of the last measurement
+    } *rb;
+    hipEvent_t rb_ev[2];
 };
 
 // Scratch of srot_backward_noalloc: one copy per GPU, held until the process
@@ -32,8 +40,8 @@ struct srot_handle {
 static __device__ __align__(256) unsigned char scratch[SROT_NOALLOC_SCRATCH_BYTES];
 
 namespace {
-// Zeroes the control words of the static scratch (the gap sweep's arrival
-// counter must start at zero): a kernel, so the call stays capturable.
+// Zeroes the control words of the static scratch (no word an earlier call
+// left is read as a flag): a kernel, so the call stays capturable.
 __global__ void noalloc_clear_kernel(int32_t *words)
 {
     if (threadIdx.x < 64) words[threadIdx.x] = 0;
@@ -255,61 +263,96 @@ int measure_gap(srot_handle *h, double *out3)
 
 }  // namespace
 
+// Pinned readback slots and their events, made once per handle.
+int ensure_readback(srot_handle *h)
+{
+    if (h->rb) return SROT_OK;
+    void *p = nullptr;
+    SROT_HIP(hipHostMalloc(&p, 2 * sizeof(srot_handle::Readback), hipHostMallocDefault));
+    for (int q = 0; q < 2; ++q) {
+        hipError_t e = hipEventCreateWithFlags(&h->rb_ev[q], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (int k = 0; k < q; ++k) (void)hipEventDestroy(h->rb_ev[k]);
+            (void)hipHostFree(p);
+            return fail(SROT_EHIP, "hipEventCreateWithFlags failed: %s", hipGetErrorString(e));
+        }
+    }
+    h->rb = (srot_handle::Readback *)p;
+    return SROT_OK;
+}
+
 // Passes are queued in batches of kSolveBatch.  The final sum of each
 // measuring sweep takes the stop test on the device; once g <= eps every
-// later kernel of the batch returns at its start, so the host reads the
-// stop word once per batch and the state is that of the stopping pass.
+// later kernel returns at its start, so the state is that of the stopping
+// pass.  The host queues batch b + 1 before it reads batch b's stop word
+// (copied to pinned memory behind the batch), so the GPU does not wait for
+// the host between batches; a batch queued after the stop does nothing.
 // steps(p, Ps) queues pass p's block steps, after(p, Ps, measured) what
 // follows the pass's sweep (the gap-adaptive sampler's global update).
-constexpr int64_t kSolveBatch = 8;
+constexpr int64_t kSolveBatch = 4;
 
 template <class Steps, class After>
 int solve_on_device(srot_handle *h, double *out3, int64_t *passes, Steps steps, After after)
 {
     *passes = 0;
     out3[0] = INFINITY; out3[1] = NAN; out3[2] = NAN;
+    int rc = ensure_readback(h);
+    if (rc != SROT_OK) return rc;
     const int64_t m = h->P.m, maxp = h->opt.max_passes;
-    int32_t *stop_w = h->S.flags + 4;  // [0] stopped, [1] its pass (low 32 bits)
+    int32_t *stop_w = h->S.flags + 4;  // [0] stopped, [1] its pass (low 32 bits), [2] team error
     srot::ProblemView Ps = h->P;
     Ps.stop = stop_w;
     SROT_HIP(hipMemsetAsync(stop_w, 0, 2 * sizeof(int32_t), h->stream));
     const int64_t k0 = h->k;
-    bool measured_any = false;
-    for (int64_t p0 = 0; p0 < maxp; p0 += kSolveBatch) {
-        const int64_t p1 = std::min(maxp, p0 + kSolveBatch);
+    // queue passes [p0, p1) and the readback of their outcome into slot q
+    auto queue = [&](int64_t p0, int64_t p1, int q) -> int {
         for (int64_t p = p0; p < p1; ++p) {
-            int rc = steps(p, Ps);
-            if (rc != SROT_OK) return rc;
+            int r = steps(p, Ps);
+            if (r != SROT_OK) return r;
             const bool measure = (p + 1) % h->opt.gap_every == 0 || p + 1 == maxp;
-            if (measure) {
+            if (measure)
                 SROT_HIP(srot::launch_gap_stop(Ps, h->S, h->stream, stop_w, h->opt.eps, (int32_t)(uint32_t)p));
-                measured_any = true;
-            }
-            rc = after(p, Ps, measure);
+            r = after(p, Ps, measure);
+            if (r != SROT_OK) return r;
+        }
+        SROT_HIP(hipMemcpyAsync(h->rb[q].words, stop_w, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipMemcpyAsync(h->rb[q].sums, h->S.meas, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipEventRecord(h->rb_ev[q], h->stream));
+        return SROT_OK;
+    };
+    if (maxp <= 0) return SROT_NOT_CONVERGED;
+    int64_t p0 = 0, p1 = std::min(maxp, kSolveBatch);
+    rc = queue(p0, p1, 0);
+    if (rc != SROT_OK) return rc;
+    bool measured_any = false;
+    for (int64_t b = 0;; ++b) {
+        const int q = (int)(b & 1);
+        // the next batch goes in before this one is read
+        const int64_t n0 = p1, n1 = std::min(maxp, p1 + kSolveBatch);
+        if (n0 < maxp) {
+            rc = queue(n0, n1, 1 - q);
             if (rc != SROT_OK) return rc;
         }
-        int32_t sw[2] = {0, 0};
-        double host[3];
-        int32_t team_err = 0;
-        SROT_HIP(hipMemcpyAsync(sw, stop_w, sizeof(sw), hipMemcpyDeviceToHost, h->stream));
-        SROT_HIP(hipMemcpyAsync(host, h->S.meas, sizeof(host), hipMemcpyDeviceToHost, h->stream));
-        if (h->S.team)
-            SROT_HIP(hipMemcpyAsync(&team_err, h->S.flags + 6, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-        SROT_HIP(hipStreamSynchronize(h->stream));
-        if (team_err)
+        SROT_HIP(hipEventSynchronize(h->rb_ev[q]));
+        const srot_handle::Readback &R = h->rb[q];
+        if (h->S.team && R.words[2])
             return fail(SROT_EHIP, "team chain: a member waited too long for the others' records; "
                                    "the plan and residual are inconsistent");
-        if (measured_any) { out3[0] = host[0]; out3[1] = host[1]; out3[2] = host[2]; }
-        if (sw[0]) {
-            // the batch holds fewer than 2^32 passes: the low bits name the pass
-            const int64_t p = p0 + (int64_t)(uint32_t)((uint32_t)sw[1] - (uint32_t)p0);
+        for (int64_t p = p0; p < p1; ++p)
+            measured_any |= (p + 1) % h->opt.gap_every == 0 || p + 1 == maxp;
+        if (measured_any) { out3[0] = R.sums[0]; out3[1] = R.sums[1]; out3[2] = R.sums[2]; }
+        if (R.words[0]) {
+            // a batch holds fewer than 2^32 passes: the low bits name the pass
+            const int64_t p = p0 + (int64_t)(uint32_t)((uint32_t)R.words[1] - (uint32_t)p0);
             *passes = p + 1;
             h->k = k0 + (p + 1) * m;  // the passes queued after it did nothing
             return SROT_OK;
         }
         *passes = p1;
+        if (n0 >= maxp) return SROT_NOT_CONVERGED;
+        p0 = n0;
+        p1 = n1;
     }
-    return SROT_NOT_CONVERGED;
 }
 
 extern "C" {
@@ -424,6 +467,9 @@ int srot_init(srot_handle **out, int64_t m, int64_t n, const void *C, const floa
     // the allocation-free backward's scratch on this device (its absence
     // only disables srot_backward_noalloc)
     if (rc == SROT_OK) h->scratch_err = scratch_address(&h->scratch);
+    // the solve loops' pinned readback words (host memory), made here so
+    // that no solve pays for the allocation
+    if (rc == SROT_OK) rc = ensure_readback(h);
     if (rc == SROT_OK && screened) {
         // FP32 screen value fma(w, r, c) against c + w r: at most 2^-22
         // (|c| + |w| |r|) off (rounding of r, w and the fma); doubled
@@ -614,38 +660,56 @@ int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma)
 }
 
 // Iterations are queued in batches; each sweep checks the device's done
-// flag, so the host reads the state once per batch.
-constexpr int64_t kFwBatch = 8;
+// flag, and the host reads the run state of batch b (copied to pinned
+// memory behind it) only after batch b + 1 is queued, so the GPU does not
+// wait for the host between batches.
+constexpr int64_t kFwBatch = 4;
 
 int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters)
 {
     if (!h || !out3 || !iters) return fail(SROT_EINVAL, "srot_fw_solve: NULL argument");
     *iters = 0;
+    int rc = ensure_readback(h);
+    if (rc != SROT_OK) return rc;
     const int64_t maxit = h->opt.max_passes;
     SROT_HIP(srot::launch_fw_reset(h->P, h->S, h->stream));
-    int64_t launched = 0;
-    int32_t state[3] = {0, 0, 0};
-    double sc[3] = {0.0, 0.0, 0.0};
-    for (;;) {
-        // sweeps launched + q for q < batch: the one numbered maxit only measures
-        const int64_t batch = std::min<int64_t>(kFwBatch, maxit + 1 - launched);
-        for (int64_t q = 0; q < batch; ++q) {
-            const int64_t it = launched + q;
+    // sweeps i0 .. i1 - 1 and the readback of the run state into slot q; the
+    // sweep numbered maxit only measures
+    auto queue = [&](int64_t i0, int64_t i1, int q) -> int {
+        for (int64_t it = i0; it < i1; ++it) {
             const srot::FwSweep f = srot::fw_sweep_args(h->S, h->opt.eps, h->opt.step_rule, it < maxit ? 1 : 0,
                                                         h->fw_k + it, nullptr);
             SROT_HIP(srot::launch_fw_iteration(h->P, h->S, f, h->stream));
         }
-        launched += batch;
-        SROT_HIP(hipMemcpyAsync(state, h->S.flags + 1, sizeof(state), hipMemcpyDeviceToHost, h->stream));
-        SROT_HIP(hipMemcpyAsync(sc, h->S.scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
-        SROT_HIP(hipStreamSynchronize(h->stream));
-        if (state[0] || launched > maxit) break;
+        SROT_HIP(hipMemcpyAsync(h->rb[q].words, h->S.flags + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                h->stream));
+        SROT_HIP(hipMemcpyAsync(h->rb[q].sums, h->S.scalars, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        SROT_HIP(hipEventRecord(h->rb_ev[q], h->stream));
+        return SROT_OK;
+    };
+    const int64_t last = maxit + 1;  // sweeps 0 .. maxit
+    int64_t i1 = std::min(last, kFwBatch);
+    rc = queue(0, i1, 0);
+    if (rc != SROT_OK) return rc;
+    const srot_handle::Readback *R = nullptr;
+    for (int64_t b = 0;; ++b) {
+        const int q = (int)(b & 1);
+        const int64_t n0 = i1, n1 = std::min(last, i1 + kFwBatch);
+        if (n0 < last) {
+            rc = queue(n0, n1, 1 - q);
+            if (rc != SROT_OK) return rc;
+        }
+        SROT_HIP(hipEventSynchronize(h->rb_ev[q]));
+        R = &h->rb[q];
+        if (R->words[0] || n0 >= last) break;  // done, or every sweep queued and read
+        i1 = n1;
     }
     SROT_HIP(srot::launch_fw_flush(h->P, h->S, h->stream));
-    *iters = state[2];
-    h->fw_k += state[2];
-    out3[0] = sc[0]; out3[1] = sc[1]; out3[2] = sc[2];
-    return state[0] ? SROT_OK : SROT_NOT_CONVERGED;
+    // [0] done, [1] step pending, [2] steps taken
+    *iters = R->words[2];
+    h->fw_k += R->words[2];
+    out3[0] = R->sums[0]; out3[1] = R->sums[1]; out3[2] = R->sums[2];
+    return R->words[0] ? SROT_OK : SROT_NOT_CONVERGED;
 }
 
 int srot_step_variant(srot_handle *h, int variant, int64_t nsteps, const int32_t *idx, int32_t *trace_j,
@@ -758,7 +822,16 @@ int srot_barycentric(srot_handle *h, float *Xhat)
     return SROT_OK;
 }
 
-void srot_destroy(srot_handle *h) { free(h); }
+void srot_destroy(srot_handle *h)
+{
+    if (!h) return;
+    if (h->rb) {
+        (void)hipStreamSynchronize(h->stream);  // no readback copy still on its way
+        (void)hipHostFree(h->rb);
+        for (hipEvent_t e : h->rb_ev) (void)hipEventDestroy(e);
+    }
+    free(h);
+}
 
 const char *srot_strerror(int status)
 {
