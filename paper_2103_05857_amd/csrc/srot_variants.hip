@@ -29,6 +29,17 @@ namespace srot {
 
 namespace {
 
+// OR of a 32-bit word over the wave, the same in every lane.
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
+{
+    v |= (uint32_t)dpp_i32<DPP_QUAD_XOR1>((int)v);
+    v |= (uint32_t)dpp_i32<DPP_QUAD_XOR2>((int)v);
+    v |= (uint32_t)dpp_i32<DPP_HALF_MIRROR>((int)v);
+    v |= (uint32_t)dpp_i32<DPP_MIRROR>((int)v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) | (uint32_t)__builtin_amdgcn_readlane((int)v, 16) |
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) | (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
 template <int NT, int CPT, int VEC, int COST, int PAIR>
 __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *__restrict__ T,
                                                          double *__restrict__ rg, uint32_t *__restrict__ M,
@@ -115,9 +126,21 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
 
         // P1 = sum t (g - G), P2 = sum t (V - g), Q1 = sum_{j != js} t^2,
         // Q2 = sum_{j != ja} t^2, t_js, t_ja, number of atoms
+        // Only the support contributes (t >= 0 and every sum starts at +0, so
+        // leaving out columns with t = 0 changes no bit); a column index u no
+        // lane of the wave holds in its support is skipped by the whole wave.
+        uint32_t nz = 0u, touch = 0u;  // support; support, FW and away vertex
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int j = owned_col<NT, VEC>(u, tid);
+            nz |= (t[u] != 0.0 ? 1u : 0u) << u;
+            touch |= (t[u] != 0.0 || j == js || j == ja ? 1u : 0u) << u;
+        }
+        const uint32_t wnz = wave_or_u32(nz), wtouch = wave_or_u32(touch);
         double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
+            if (!((wnz >> u) & 1u)) continue;  // uniform over the wave
             const int j = owned_col<NT, VEC>(u, tid);
             const bool on = t[u] > 0.0;
             acc[0] += t[u] * (vv[u] - G);
@@ -155,10 +178,12 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
         else gamma = num / den < gmax ? num / den : gmax;
         const bool drop = !fw_dir && gamma > 0.0 && gamma == gmax;
 
-        // update this thread's entries, r and the support bits
+        // update this thread's entries, r and the support bits (only the
+        // support and the two vertices can change)
         uint32_t nm = mk;
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
+            if (!((wtouch >> u) & 1u)) continue;  // uniform over the wave
             const int j = owned_col<NT, VEC>(u, tid);
             double tn;
             if (fw_dir) tn = (1.0 - gamma) * t[u] + ((j == js) ? gamma * ai : 0.0);
