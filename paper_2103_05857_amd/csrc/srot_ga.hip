@@ -36,6 +36,17 @@ namespace srot {
 
 namespace {
 
+// OR of a 32-bit word over the wave, the same in every lane.
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
+{
+    v |= (uint32_t)dpp_i32<DPP_QUAD_XOR1>((int)v);
+    v |= (uint32_t)dpp_i32<DPP_QUAD_XOR2>((int)v);
+    v |= (uint32_t)dpp_i32<DPP_HALF_MIRROR>((int)v);
+    v |= (uint32_t)dpp_i32<DPP_MIRROR>((int)v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) | (uint32_t)__builtin_amdgcn_readlane((int)v, 16) |
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) | (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
 // Uniform double in [0, 1) from output k of the block-index stream.
 __device__ __forceinline__ double philox_unit(uint64_t seed, int64_t k)
 {
@@ -124,14 +135,22 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
             if (fb) {
                 const int fl = __ffsll((long long)fb) - 1;
                 if (lane == fl) {
+                    // the running sum in row order over the chunk, its
+                    // entries read eight at a time
                     double c = lo;
                     int lp = -1;
-                    for (int q = q0; q < q1; ++q) {
-                        const double wq = s_W[q];
-                        if (wq > 0.0) {
-                            lp = q;
-                            c += wq;
-                            if (c > x) { cand = q; break; }
+                    for (int q8 = q0; q8 < q1 && cand < 0; q8 += 8) {
+                        double wv[8];
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) wv[e] = (q8 + e < q1) ? s_W[q8 + e] : 0.0;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const double wq = wv[e];
+                            if (cand < 0 && wq > 0.0) {
+                                lp = q8 + e;
+                                c += wq;
+                                if (c > x) cand = q8 + e;
+                            }
                         }
                     }
                     if (cand < 0) cand = lp;
@@ -159,13 +178,21 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
         if constexpr (FUSED) { x0 = P.X[3 * i]; x1 = P.X[3 * i + 1]; x2 = P.X[3 * i + 2]; }
         else load_cost_row<NT, CPT, VEC, CT>(C + base, n, tid, cv);
         double t[CPT], cc[CPT];
+        // the row's plan entries are requested with its mask word and cost
+        // (one round trip instead of two) and kept where the mask has a bit
+        double tl[CPT];
+#pragma unroll
+        for (int u2 = 0; u2 < CPT; ++u2) {
+            const int j = owned_col<NT, VEC>(u2, tid);
+            tl[u2] = T[base + (j < n ? j : n - 1)];
+        }
         double best = INFINITY;
         int bj = 0x7fffffff;
 #pragma unroll
         for (int u2 = 0; u2 < CPT; ++u2) {
             const int j = owned_col<NT, VEC>(u2, tid);
             const int jc = j < n ? j : n - 1;
-            t[u2] = (mk & (1u << u2)) ? T[base + j] : 0.0;
+            t[u2] = (mk & (1u << u2)) ? tl[u2] : 0.0;
             if constexpr (FUSED) cc[u2] = sqdist(x0, x1, x2, P.Y[3 * jc], P.Y[3 * jc + 1], P.Y[3 * jc + 2]);
             else cc[u2] = (double)cv[u2];
             const double v = (j < n) ? cc[u2] + w * r[u2] : INFINITY;
@@ -174,9 +201,20 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
         block_argmin<NW>(best, bj, s_v[par], s_j[par]);
         const double G = best;
         const int jstar = bj;
+        // only the support contributes (t >= 0, sums from +0: leaving out
+        // t = 0 changes no bit); column slots no lane holds are skipped by
+        // the whole wave, and only the support and j* can change
+        const int jg = jstar / VEC;
+        const int us = ((jg % NT) == tid) ? (jg / NT) * VEC + (jstar % VEC) : -1;
+        uint32_t nz = 0u;
+#pragma unroll
+        for (int u2 = 0; u2 < CPT; ++u2) nz |= (t[u2] != 0.0 ? 1u : 0u) << u2;
+        const uint32_t wnz = wave_or_u32(nz);
+        const uint32_t wtouch = wave_or_u32(nz | (us >= 0 ? 1u << us : 0u));
         double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int u2 = 0; u2 < CPT; ++u2) {
+            if (!((wnz >> u2) & 1u)) continue;  // uniform over the wave
             const bool st = (owned_col<NT, VEC>(u2, tid) == jstar);
             acc[0] += t[u2] * ((cc[u2] + w * r[u2]) - G);
             acc[1] += st ? 0.0 : t[u2] * t[u2];
@@ -185,16 +223,15 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
         block_sum<NW, 3>(acc, s_sum[par]);
         const double gamma = step_size(rule, k0 + s, m, w, acc[0], acc[1], acc[2], ai);
         const double gadd = gamma * ai;
-        const int jg = jstar / VEC;
-        const int us = ((jg % NT) == tid) ? (jg / NT) * VEC + (jstar % VEC) : -1;
-        uint32_t nm = 0u;
+        uint32_t nm = mk;
 #pragma unroll
         for (int u2 = 0; u2 < CPT; ++u2) {
+            if (!((wtouch >> u2) & 1u)) continue;  // uniform over the wave
             const double tn = blend(t[u2], gamma, (u2 == us) ? gadd : 0.0);
             if (tn != t[u2]) T[base + owned_col<NT, VEC>(u2, tid)] = tn;
             r[u2] += tn - t[u2];
             t[u2] = tn;
-            nm |= (tn != 0.0) ? (1u << u2) : 0u;
+            nm = (tn != 0.0) ? (nm | (1u << u2)) : (nm & ~(1u << u2));
         }
         if (nm != mk) M[(size_t)i * NT + tid] = nm;
 
@@ -209,8 +246,12 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
         }
         block_argmin<NW>(best2, bj2, s_v2[par], s_j2[par]);
         double gs[1] = {0.0};
+        const uint32_t wnm = wave_or_u32(nm);
 #pragma unroll
-        for (int u2 = 0; u2 < CPT; ++u2) gs[0] += t[u2] * ((cc[u2] + w * r[u2]) - best2);
+        for (int u2 = 0; u2 < CPT; ++u2) {
+            if (!((wnm >> u2) & 1u)) continue;  // uniform over the wave
+            gs[0] += t[u2] * ((cc[u2] + w * r[u2]) - best2);
+        }
         block_sum<NW, 1>(gs, s_sum2[par]);
         const double gi = gs[0];
         if (tid == i / L) {
@@ -218,6 +259,9 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
             Wg[i] = gi;
             cs = 0.0;
             lastpos = -1;
+            // the chunk sum again in row order; the reads are independent,
+            // so unrolling lets them be requested together
+#pragma unroll 8
             for (int q = q0; q < q1; ++q) {
                 const double v = s_W[q];
                 cs += v;
