@@ -401,7 +401,8 @@ int srot_init_batched(srot_batch **out, int32_t count, const int64_t *m, const i
  * synchronises.  Host outputs, each optional: out3 (count x 3: g, f, D at
  * the last gap sweep), passes (count), status (count: SROT_OK or
  * SROT_NOT_CONVERGED).  Returns SROT_OK when every problem converged,
- * SROT_NOT_CONVERGED otherwise.  Each call also reorders the problems'
+ * SROT_NOT_CONVERGED otherwise (SROT_EINVAL if a problem's kernel did not
+ * match its tile shape, an internal error that leaves its results unset).  Each call also reorders the problems'
  * start order for the next call (longest measured run time first); a
  * problem's results do not depend on that order. */
 int srot_solve_batched(srot_batch *h, double *out3, int64_t *passes, int32_t *status);

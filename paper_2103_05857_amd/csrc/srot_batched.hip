@@ -397,16 +397,27 @@ __global__ __launch_bounds__(NT) void batch_solve_kernel(const float *__restrict
 {
     const int32_t p = order[blockIdx.x];
     const BatchProblem bp = probs[p];
+    bool solved = false;
     switch (bp.tile) {
 #define SROT_BCASE(ID_, NT_, CPT_, VEC_)                                                      \
     case ID_:                                                                                \
-        if constexpr (NT_ == NT && (NT != 256 || (VEC_ == 4) == (V4 != 0)))                  \
+        if constexpr (NT_ == NT && (NT != 256 || (VEC_ == 4) == (V4 != 0))) {                \
             batch_solve_one<NT_, CPT_, VEC_>(C, a, b, Tar, rar, Mar, idxar, bp, p, prm, res); \
+            solved = true;                                                                   \
+        }                                                                                    \
         break;
         SROT_BATCH_TILES(SROT_BCASE)
 #undef SROT_BCASE
     default:
         break;
+    }
+    if (!solved && threadIdx.x == 0) {
+        // a tile outside this launch's class (not produced by the host):
+        // reported, never left as an earlier solve's result
+        BatchResult out;
+        out.g = NAN; out.f = NAN; out.D = NAN; out.passes = 0; out.status = SROT_EINVAL; out.pad = 0;
+        out.ticks = 0;
+        res[p] = out;
     }
 }
 
@@ -835,12 +846,15 @@ int srot_solve_batched(srot_batch *h, double *out3, int64_t *passes, int32_t *st
                               h->stream));
     SROT_HIP_B(hipStreamSynchronize(h->stream));
     bool all = true;
+    int32_t bad = -1;
     for (int32_t p = 0; p < h->count; ++p) {
         if (out3) { out3[3 * p] = res[p].g; out3[3 * p + 1] = res[p].f; out3[3 * p + 2] = res[p].D; }
         if (passes) passes[p] = res[p].passes;
         if (status) status[p] = res[p].status;
         all &= (res[p].status == SROT_OK);
+        if (res[p].status < 0 && bad < 0) bad = p;
     }
+    if (bad >= 0) return fail(SROT_EINVAL, "srot_solve_batched: problem %d was launched with a tile of another class", bad);
     // the next solve starts each class's longest-running problems first
     // (the results do not depend on the order)
     std::vector<int32_t> next = h->order;
