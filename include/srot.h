@@ -264,7 +264,7 @@ int srot_backward_noalloc(srot_handle *h, double grad_out, void *dC, float *dX, 
  *   gamma = clip(-<g, d> / (w ||d||^2), 0, gamma_max)
  *   (eq. SemiRelaxedBCAFWStep); reaching gamma_max on an away or pairwise
  *   direction empties atom ja exactly.
- * Needs opt->step_rule == SROT_ELS and rows of at most 4096 columns.
+ * Needs opt->step_rule == SROT_ELS and rows of at most 8192 columns.
  *   idx          device block indices, or NULL for the handle's sampler.
  *   trace_j      device int32 per step (optional): js.
  *   trace_away   device int32 per step (optional): ja, or -1 - ja when the
@@ -285,7 +285,7 @@ int srot_solve_variant(srot_handle *h, int variant, double *out3, int64_t *passe
  * BCFW block step of srot_step on it (opt->step_rule), and stores the row's
  * gap at the new plan, g_i = <t_i - s_i, c_i + w r> (eq. AppenEq:Gi, >= 0).
  * The global update recomputes every W_i at the current plan.
- * Rows of at most 4096 columns and at most 16384 rows.
+ * Rows of at most 8192 columns and at most 16384 rows.
  * The initial constant 2^300 is exact under addition and absorbs every real
  * row gap, so rows not yet visited are drawn (uniformly) before any other. */
 #define SROT_GA_INIT 0x1p300

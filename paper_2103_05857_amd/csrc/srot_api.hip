@@ -232,7 +232,7 @@ int variant_ok(srot_handle *h, int variant, const char *who)
     if (h->opt.step_rule != SROT_ELS)
         return fail(SROT_EINVAL, "%s: away and pairwise steps use the exact line search (SROT_ELS)", who);
     if (!srot::active_steps_supported(h->S))
-        return fail(SROT_EINVAL, "%s: away and pairwise steps support rows of at most 4096 columns", who);
+        return fail(SROT_EINVAL, "%s: away and pairwise steps support rows of at most 8192 columns", who);
     return SROT_OK;
 }
 
@@ -240,7 +240,7 @@ int ga_ok(srot_handle *h, const char *who)
 {
     if (!h) return fail(SROT_EINVAL, "%s: NULL handle", who);
     if (!srot::ga_supported(h->P, h->S))
-        return fail(SROT_EINVAL, "%s: gap-adaptive sampling supports at most %d rows of at most 4096 columns", who,
+        return fail(SROT_EINVAL, "%s: gap-adaptive sampling supports at most %d rows of at most 8192 columns", who,
                     (int)srot::GA_MAX_ROWS);
     return SROT_OK;
 }

@@ -299,6 +299,9 @@ __global__ void ga_fill_kernel(int32_t m, const double *__restrict__ src, double
 #define SROT_GA_V4(X) \
     X(64, 4, 4) X(128, 4, 4) X(256, 4, 4) X(256, 8, 4) X(256, 16, 4)
 
+// The wide-row ownership of a handle for 4097-8192 columns.
+bool wide_ga_layout(const Ownership &o) { return !o.reg && o.nt == 512 && o.vec == 1 && o.words == 1 && o.cpt <= 16; }
+
 template <int COST>
 hipError_t launch_ga_cost(const ProblemView &P, const DeviceState &S, const double *u, uint64_t seed, int64_t k0,
                           int64_t nsteps, int rule, int32_t *ti, int32_t *tj, double *tg, double *tgi,
@@ -319,6 +322,17 @@ hipError_t launch_ga_cost(const ProblemView &P, const DeviceState &S, const doub
     if constexpr (COST == SROT_COST_F32) { SROT_GA_V4(SROT_GAK) }
     if constexpr (COST == SROT_COST_F64) { SROT_GA_V2(SROT_GAK) }
 #undef SROT_GAK
+    // rows of 4097-8192 columns: the handle's wide ownership (512 threads,
+    // at most 16 single columns each, one mask word) as a 512 x 16 x 1 tile;
+    // slots past the row's width lie beyond column n
+    if (wide_ga_layout(o)) {
+        const void *fn = (const void *)&ga_step_kernel<512, 16, 1, COST>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((ga_step_kernel<512, 16, 1, COST>), dim3(1), dim3(512), lds, st, P, S.T, S.r, S.mask,
+                           S.ga_w, u, seed, k0, nsteps, rule, ti, tj, tg, tgi);
+        return hipGetLastError();
+    }
     return hipErrorInvalidConfiguration;
 }
 
@@ -326,7 +340,7 @@ hipError_t launch_ga_cost(const ProblemView &P, const DeviceState &S, const doub
 
 bool ga_supported(const ProblemView &P, const DeviceState &S)
 {
-    return S.own.reg && S.own.nt <= 256 && P.m <= GA_MAX_ROWS;
+    return ((S.own.reg && S.own.nt <= 256) || wide_ga_layout(S.own)) && P.m <= GA_MAX_ROWS;
 }
 
 hipError_t launch_ga_steps(const ProblemView &P, const DeviceState &S, const double *u, uint64_t seed, int64_t k0,

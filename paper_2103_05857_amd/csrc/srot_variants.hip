@@ -230,6 +230,9 @@ __global__ __launch_bounds__(NT) void active_step_kernel(ProblemView P, double *
 #define SROT_VAR_V4(X) \
     X(64, 4, 4) X(128, 4, 4) X(256, 4, 4) X(256, 8, 4) X(256, 16, 4)
 
+// The wide-row ownership of a handle for 4097-8192 columns.
+bool wide_active_layout(const Ownership &o) { return !o.reg && o.nt == 512 && o.vec == 1 && o.words == 1 && o.cpt <= 16; }
+
 template <int COST, int PAIR>
 hipError_t launch_active_cost(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t nsteps,
                               int32_t *tj, int32_t *ta, double *tg, hipStream_t st)
@@ -245,6 +248,14 @@ hipError_t launch_active_cost(const ProblemView &P, const DeviceState &S, const 
     if constexpr (COST == SROT_COST_F32) { SROT_VAR_V4(SROT_ACT) }
     if constexpr (COST == SROT_COST_F64) { SROT_VAR_V2(SROT_ACT) }
 #undef SROT_ACT
+    // rows of 4097-8192 columns: the handle's wide ownership (512 threads,
+    // at most 16 single columns each, one mask word) is the layout of the
+    // 512 x 16 x 1 kernel; slots past the row's width lie beyond column n
+    if (wide_active_layout(o)) {
+        hipLaunchKernelGGL((active_step_kernel<512, 16, 1, COST, PAIR>), dim3(1), dim3(512), 0, st, P, S.T, S.r,
+                           S.mask, idx, nsteps, tj, ta, tg);
+        return hipGetLastError();
+    }
     return hipErrorInvalidConfiguration;
 }
 
@@ -253,7 +264,7 @@ hipError_t launch_active_cost(const ProblemView &P, const DeviceState &S, const 
 bool active_steps_supported(const DeviceState &S)
 {
     const Ownership &o = S.own;
-    return o.reg && o.nt <= 256;
+    return (o.reg && o.nt <= 256) || wide_active_layout(o);
 }
 
 hipError_t launch_active_steps(const ProblemView &P, const DeviceState &S, int pairwise, const int32_t *idx,

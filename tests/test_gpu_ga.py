@@ -74,6 +74,8 @@ def _same_step(otr, k, gi, gj, gg, gq):
     ("sqeuclid", None, 200, 333, 2.0),
     ("stored", np.float32, 97, 4096, 1.0),
     ("stored", np.float32, 5000, 130, 1.0),        # 79 rows per thread chunk
+    ("stored", np.float32, 40, 6000, 1.0),         # wide rows: 512 threads x 12 columns
+    ("sqeuclid", None, 30, 7000, 2.0),
 ])
 def test_ga_traces_match_oracle(rule, cost_mode, dtype, m, n, w):
     d = I.problem_mixture(31, m, n, cost_dtype=dtype or np.float32)
@@ -109,6 +111,7 @@ def test_ga_traces_match_oracle(rule, cost_mode, dtype, m, n, w):
 @pytest.mark.parametrize("cost_mode,dtype,m,n,w", [
     ("stored", np.float64, 48, 96, 1.0),
     ("sqeuclid", None, 40, 77, 2.0),
+    ("stored", np.float64, 24, 5000, 1.0),
 ])
 def test_every_step_from_the_gpu_state(cost_mode, dtype, m, n, w):
     """Refreshed weights first (so that rows are drawn by their real gaps),
@@ -244,8 +247,8 @@ def test_ga_argument_checks():
     with pytest.raises(S.SrotError):
         S.srot_step_ga(sol.h, -1)
     sol.close()
-    d = I.problem_mixture(36, 10, 5000, cost_dtype=np.float32)
+    d = I.problem_mixture(36, 10, 9000, cost_dtype=np.float32)
     sol, _ = _pair(d, "stored", 1.0)
     with pytest.raises(S.SrotError):
-        S.srot_step_ga(sol.h, 5)                                  # rows wider than 4096 columns
+        S.srot_step_ga(sol.h, 5)                                  # rows wider than 8192 columns
     sol.close()

@@ -89,6 +89,8 @@ def _first_divergence(otr, gj, ga, gg, sizes_may_differ=False):
     ("stored", np.float32, 300, 700, 0.5),
     ("sqeuclid", None, 200, 333, 2.0),
     ("stored", np.float32, 97, 4096, 1.0),
+    ("stored", np.float32, 40, 6000, 1.0),         # wide rows: 512 threads x 12 columns
+    ("sqeuclid", None, 30, 8192, 1.0),
 ])
 def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
     """Every step of six passes in lockstep: both sides run from a common
@@ -142,6 +144,7 @@ def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
     ("stored", np.float64, 48, 96, 1.0),
     ("stored", np.float32, 60, 300, 0.5),
     ("sqeuclid", None, 40, 77, 2.0),
+    ("stored", np.float64, 24, 5000, 1.0),
 ])
 def test_every_step_from_the_gpu_state(variant, cost_mode, dtype, m, n, w):
     """The oracle takes each step from the GPU's own state (plan and
