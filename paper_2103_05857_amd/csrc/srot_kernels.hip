@@ -872,7 +872,7 @@ constexpr int GAP_MW = 8;  // mask words per lane and row read ahead
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int COST, int R, int GU, bool FW, bool ROT>
-__global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, double *__restrict__ T,
+__global__ __launch_bounds__(GAP_NT) __attribute__((amdgpu_waves_per_eu(2))) void gap_stream_kernel(ProblemView P, double *__restrict__ T,
                                                             double *__restrict__ rg,
                                                             uint32_t *__restrict__ M, Ownership own,
                                                             double *__restrict__ row_G,
@@ -969,7 +969,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
                 }
             }
         };
-        issue(ca, ra, 0);
+        if constexpr (!FW) issue(ca, ra, 0);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             // rows past the end read an empty range: no support, no cost
@@ -1101,6 +1101,7 @@ __global__ __launch_bounds__(GAP_NT) void gap_stream_kernel(ProblemView P, doubl
             for (int k = 0; k < R; ++k) gather(k);
         }
 
+        if constexpr (FW) issue(ca, ra, 0);
         for (int q0 = 0; q0 < nq; q0 += 2 * GU) {
             issue(cb, rb, q0 + GU);
             consume(ca, ra, q0);
@@ -1567,7 +1568,7 @@ static hipError_t launch_gap_stream(const ProblemView &P, const DeviceState &S, 
 {
     constexpr int GU = (COST == SROT_COST_F32) ? 2 : 4;
     if (P.n >= 8192) {
-        if (fw) return launch_gap_stream_rg<COST, 2, GU, true>(P, S, fw, st, GAP_MAX_BLOCKS, nb_out);
+        if (fw) return launch_gap_stream_rg<COST, 4, GU / 2, true>(P, S, fw, st, 512, nb_out);
         return launch_gap_stream_rg<COST, 4, GU / 2, true>(P, S, fw, st, 512, nb_out);
     }
     return launch_gap_stream_rg<COST, 2, GU, false>(P, S, fw, st, GAP_MAX_BLOCKS, nb_out);
