@@ -110,6 +110,11 @@ hipError_t launch_cost_bounds(const ProblemView &P, const DeviceState &S, double
 hipError_t launch_chain_screened(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t k0,
                                  int64_t nsteps, int rule, int32_t *trace_j, double *trace_gamma,
                                  hipStream_t stream);
+// Away (pairwise = 0) or pairwise (pairwise = 1) block steps on the screened
+// chain (same conditions as above; ELS).
+hipError_t launch_active_screened(const ProblemView &P, const DeviceState &S, int pairwise, const int32_t *idx,
+                                  int64_t nsteps, int32_t *trace_j, int32_t *trace_away, double *trace_gamma,
+                                  hipStream_t stream);
 // {squared diameter of the points' bounding box, max(sum a, max b)} into out2.
 hipError_t launch_screen_bounds(const ProblemView &P, double *out2, hipStream_t stream);
 

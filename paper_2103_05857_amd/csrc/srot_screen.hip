@@ -75,7 +75,16 @@ __device__ __forceinline__ float wave_min_f32(float v)
 // gfx9 s_waitcnt immediates: lgkmcnt(0) with vmcnt(vm)
 constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | (7 << 4) | ((vm >> 4) << 14); }
 
-template <int CPT, bool TRACE>
+// VAR = 1 / 2: the same chain takes away steps (Alg. A.2) or pairwise steps
+// (Alg. A.3) instead of BCFW steps (ELS only).  The stepper then also finds
+// the away vertex ja, the lowest-index argmax of c_ij + w r_j over the
+// support (with the FW vertex, one wave reduction each), adds the four
+// further support sums of the away direction, picks the direction and the
+// step size clip(-<g, d> / (w ||d||^2), 0, gamma_max), and updates the
+// support, emptying atom ja exactly when gamma reaches gamma_max.  A step
+// on an away or pairwise direction lowers only t_ija, by at most t_ija: its
+// entry in the screen's decrease allowance.
+template <int CPT, bool TRACE, int VAR = 0>
 __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, double *__restrict__ T,
                                                                double *__restrict__ rg,
                                                                uint32_t *__restrict__ M,
@@ -83,13 +92,15 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                                                                int64_t nsteps, int rule,
                                                                int32_t *__restrict__ trace_j,
                                                                double *__restrict__ trace_gamma,
+                                                               int32_t *__restrict__ trace_away,
                                                                int64_t *__restrict__ slow_steps, double err_c)
 {
     if (P.stop && *P.stop) return;  // the solve has stopped
     static_assert(CPT == 4 || CPT == 8 || CPT == 16, "4 owner threads x CPT columns per lane");
     constexpr int NC = 256 * CPT;   // columns of the ownership (n <= NC)
     constexpr int G = CPT / 4;      // 16-byte groups per owner thread
-    constexpr int NST = SC_KS + 1 + 1 + (TRACE ? 2 : 0);  // stores issued by every step
+    static_assert(VAR >= 0 && VAR <= 2, "BCFW, away or pairwise steps");
+    constexpr int NST = SC_KS + 1 + 1 + (TRACE ? (VAR ? 3 : 2) : 0);  // stores issued by every step
     __shared__ __align__(16) double r64[NC];
     __shared__ __align__(16) float r32[NC];
     // a prepared row: header (row, a_i, tau, overflow flag) and, per lane,
@@ -185,6 +196,40 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
 #pragma unroll
                 for (int k = 0; k < SC_KS; ++k) sr[k] = r64[sq[k] >= 0 ? sq[k] : 0];
 
+                // away / pairwise: the away vertex over the support (this
+                // lane's entries, then the wave; lowest column on ties)
+                double vaw = -INFINITY;
+                int jaw = 0x7fffffff;
+                if constexpr (VAR != 0) {
+                    auto away_take = [&](double t, double vk, int col) {
+                        const bool take = t > 0.0 && (vk > vaw || (vk == vaw && col < jaw));
+                        vaw = take ? vk : vaw;
+                        jaw = take ? col : jaw;
+                    };
+                    if (!stale) {
+#pragma unroll
+                        for (int k = 0; k < SC_KS; ++k)
+                            if (sq[k] >= 0) away_take(st[k], (double)sc[k] + w * sr[k], sq[k]);
+                    } else {
+                        const uint32_t *__restrict__ mrow = M + (size_t)i * 256;
+                        const double *__restrict__ trow = T + (size_t)i * (size_t)n;
+                        const float *__restrict__ crow = C + (size_t)i * (size_t)n;
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            uint32_t bits = mrow[lane + 64 * h];
+                            while (bits) {
+                                const int u = __ffs(bits) - 1;
+                                bits &= bits - 1u;
+                                const int col = owned_col<256, 4>(u, lane + 64 * h);
+                                away_take(trow[col], (double)crow[col] + w * r64[col], col);
+                            }
+                        }
+                    }
+                    double nv = -vaw;
+                    wave_argmin(nv, jaw);
+                    vaw = -nv;
+                }
+
                 // LMO over the candidates, accepted against the screen's bound
                 const double vc = cj >= 0 ? (double)cc + w * rc : INFINITY;
                 double vstar = wave_min(vc);
@@ -255,6 +300,18 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 double pp = 0.0, q2 = 0.0, tj = 0.0, ts = 0.0;
                 double toff_max = 0.0;  // largest entry off the vertex: it drops by gamma times it
                 bool star_l = false;
+                // away / pairwise: sum t (V - g) over the support, sum of t^2
+                // off ja, t_ija and the number of atoms
+                double pa = 0.0, qa = 0.0, ta = 0.0, na = 0.0;
+                auto away_sums = [&](double t, double vk, int col) {
+                    if constexpr (VAR != 0) {
+                        const bool on = t > 0.0;
+                        pa += on ? t * (vaw - vk) : 0.0;
+                        qa += (col == jaw) ? 0.0 : t * t;
+                        ta += (col == jaw) ? t : 0.0;
+                        na += on ? 1.0 : 0.0;
+                    }
+                };
                 if (!stale) {
 #pragma unroll
                     for (int k = 0; k < SC_KS; ++k) {
@@ -268,6 +325,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                         ts += t;
                         toff_max = fmax(toff_max, atj ? 0.0 : t);
                         star_l |= atj;
+                        if (has) away_sums(t, vk, sq[k]);
                     }
                 } else {
                     ++n_slow;
@@ -292,6 +350,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                             ts += t;
                             toff_max = fmax(toff_max, atj ? 0.0 : t);
                             star_l |= atj;
+                            away_sums(t, vk, col);
                         }
                     }
 #pragma unroll
@@ -300,6 +359,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 // each partial summed over the lanes holding nonzeros, in lane order
                 // (rows have few nonzeros: cheaper than a full wave reduction)
                 double sp = 0.0, sq2 = 0.0, stj = 0.0, smax = 0.0;
+                double spa = 0.0, sqa = 0.0, sta = 0.0, sna = 0.0;
                 {
                     unsigned long long act = __ballot(ts != 0.0 || pp != 0.0 || q2 != 0.0 || tj != 0.0);
                     while (act) {
@@ -309,11 +369,59 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                         sq2 += readlane_f64(q2, l);
                         stj += readlane_f64(tj, l);
                         smax = fmax(smax, readlane_f64(toff_max, l));
+                        if constexpr (VAR != 0) {
+                            spa += readlane_f64(pa, l);
+                            sqa += readlane_f64(qa, l);
+                            sta += readlane_f64(ta, l);
+                            sna += readlane_f64(na, l);
+                        }
                     }
                 }
                 const bool star_in = __any(star_l);
-                const double gamma = step_size(rule, k0 + s, m, w, sp, sq2, stj, ai);
+                double gamma;
+                bool fw_dir = true, drop = false;
+                if constexpr (VAR == 0) {
+                    gamma = step_size(rule, k0 + s, m, w, sp, sq2, stj, ai);
+                } else {
+                    // direction and gamma_max (Alg. A.2 / A.3), then the exact
+                    // line search clipped to [0, gamma_max]
+                    const double alpha = sta / ai;
+                    double num, den, gmax;
+                    if constexpr (VAR == 2) {
+                        fw_dir = false;
+                        num = (jstar != jaw) ? ai * (vaw - vstar) : 0.0;
+                        den = (jstar != jaw) ? w * (2.0 * ai * ai) : 0.0;
+                        gmax = alpha;
+                    } else {
+                        fw_dir = sna == 1.0 || jaw == jstar || sp >= spa;
+                        if (fw_dir) {
+                            num = sp;
+                            den = w * (sq2 + (stj - ai) * (stj - ai));
+                            gmax = 1.0;
+                        } else {
+                            num = spa;
+                            den = w * (sqa + (sta - ai) * (sta - ai));
+                            gmax = alpha / (1.0 - alpha);
+                        }
+                    }
+                    if (!(num > 0.0)) gamma = 0.0;
+                    else if (den == 0.0) gamma = gmax;
+                    else gamma = num / den < gmax ? num / den : gmax;
+                    drop = !fw_dir && gamma > 0.0 && gamma == gmax;
+                }
                 const double gadd = gamma * ai;
+                // the new entry of a support column (ats: the FW vertex, ata: the away vertex)
+                auto new_entry = [&](double t, bool ats, bool ata) {
+                    if constexpr (VAR == 0) {
+                        return blend(t, gamma, ats ? gadd : 0.0);
+                    } else {
+                        double tn;
+                        if (fw_dir) tn = blend(t, gamma, ats ? gadd : 0.0);
+                        else if constexpr (VAR == 2) tn = (jstar == jaw) ? t : (ats ? t + gadd : (ata ? t - gadd : t));
+                        else tn = (1.0 + gamma) * t - (ata ? gadd : 0.0);
+                        return (drop && ata) ? 0.0 : tn;
+                    }
+                };
 
                 // t_i <- (1 - gamma) t_i + gamma a_i e_j*, r <- r + (t_i new - t_i old)
                 double tnv[SC_KS];
@@ -323,7 +431,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 for (int k = 0; k < SC_KS; ++k) {
                     const bool has = sq[k] >= 0;
                     const bool atj = has && sq[k] == jstar;
-                    const double tn = blend(st[k], gamma, atj ? gadd : 0.0);
+                    const double tn = new_entry(st[k], atj, has && sq[k] == jaw);
                     const bool put = has && tn != st[k];
                     const int col = has ? sq[k] : 0;
                     const double rn = sr[k] + (tn - st[k]);
@@ -346,7 +454,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                             bits &= bits - 1u;
                             const int col = owned_col<256, 4>(u, lane + 64 * h);
                             const double t = trow[col];
-                            const double tn = blend(t, gamma, col == jstar ? gadd : 0.0);
+                            const double tn = new_entry(t, col == jstar, col == jaw);
                             if (tn != t) {
                                 const double rn = r64[col] + (tn - t);
                                 r64[col] = rn;
@@ -358,7 +466,9 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     }
                     drain_memory();
                 }
-                const double tsn = blend(0.0, gamma, gadd);
+                // the FW vertex when it is not in the support (an away
+                // direction leaves it at 0)
+                const double tsn = fw_dir ? blend(0.0, gamma, gadd) : ((VAR == 2 && jstar != jaw) ? gadd : 0.0);
                 const int oq = (jstar >> 2) & 255;
                 const int hs = oq >> 6, us = ((jstar >> 10) << 2) | (jstar & 3);
                 const bool put_s = ((oq & 63) == lane) && !star_in && tsn != 0.0;
@@ -383,6 +493,10 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                     const __amdgpu_buffer_rsrc_t rs_tg = buf_rsrc(trace_gamma, trace_gamma ? (unsigned)nsteps * 8u : 0u);
                     buf_store_u32((unsigned)jstar, rs_tj, lane == 0 ? (unsigned)s * 4u : kOOB);
                     buf_store_f64(gamma, rs_tg, lane == 0 ? (unsigned)s * 8u : kOOB);
+                    if constexpr (VAR != 0) {
+                        const __amdgpu_buffer_rsrc_t rs_ta = buf_rsrc(trace_away, trace_away ? (unsigned)nsteps * 4u : 0u);
+                        buf_store_u32((unsigned)(fw_dir ? -1 - jaw : jaw), rs_ta, lane == 0 ? (unsigned)s * 4u : kOOB);
+                    }
                 }
                 // rare: nonzeros that became 0 leave the support (and every word
                 // of a row re-read from the plan is rewritten as computed)
@@ -409,7 +523,10 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 hist[0] = i;
 #pragma unroll
                 for (int k = SC_DECN - 1; k > 0; --k) dec[k] = dec[k - 1];
-                dec[0] = gamma * smax;
+                // the largest decrease of an r_j in this step: gamma times the
+                // largest entry off the FW vertex, or t_ija on an away or
+                // pairwise direction
+                dec[0] = fw_dir ? gamma * smax : sta;
                 // every store of earlier steps is complete before the barrier
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(NST));
             }
@@ -638,18 +755,19 @@ hipError_t launch_cost_bounds(const ProblemView &P, const DeviceState &S, double
     return hipGetLastError();
 }
 
-hipError_t launch_chain_screened(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t k0,
-                                 int64_t nsteps, int rule, int32_t *tj, double *tg, hipStream_t st)
+template <int VAR>
+static hipError_t launch_screened_var(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t k0,
+                                      int64_t nsteps, int rule, int32_t *tj, double *tg, int32_t *ta, hipStream_t st)
 {
-    const bool trace = tj || tg;
+    const bool trace = tj || tg || ta;
 #define SROT_SCREENED(CPT_)                                                                          \
     if (S.own.cpt == CPT_) {                                                                         \
         if (trace)                                                                                   \
-            hipLaunchKernelGGL((chain_screened_kernel<CPT_, true>), dim3(1), dim3(SC_NT), 0, st, P, S.T, \
-                               S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.slow_steps, S.screen_err); \
+            hipLaunchKernelGGL((chain_screened_kernel<CPT_, true, VAR>), dim3(1), dim3(SC_NT), 0, st, P, S.T, \
+                               S.r, S.mask, idx, k0, nsteps, rule, tj, tg, ta, S.slow_steps, S.screen_err); \
         else                                                                                         \
-            hipLaunchKernelGGL((chain_screened_kernel<CPT_, false>), dim3(1), dim3(SC_NT), 0, st, P, S.T, \
-                               S.r, S.mask, idx, k0, nsteps, rule, tj, tg, S.slow_steps, S.screen_err); \
+            hipLaunchKernelGGL((chain_screened_kernel<CPT_, false, VAR>), dim3(1), dim3(SC_NT), 0, st, P, S.T, \
+                               S.r, S.mask, idx, k0, nsteps, rule, tj, tg, ta, S.slow_steps, S.screen_err); \
         return hipGetLastError();                                                                    \
     }
     SROT_SCREENED(4)
@@ -657,6 +775,19 @@ hipError_t launch_chain_screened(const ProblemView &P, const DeviceState &S, con
     SROT_SCREENED(16)
 #undef SROT_SCREENED
     return hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_chain_screened(const ProblemView &P, const DeviceState &S, const int32_t *idx, int64_t k0,
+                                 int64_t nsteps, int rule, int32_t *tj, double *tg, hipStream_t st)
+{
+    return launch_screened_var<0>(P, S, idx, k0, nsteps, rule, tj, tg, nullptr, st);
+}
+
+hipError_t launch_active_screened(const ProblemView &P, const DeviceState &S, int pairwise, const int32_t *idx,
+                                  int64_t nsteps, int32_t *tj, int32_t *ta, double *tg, hipStream_t st)
+{
+    if (pairwise) return launch_screened_var<2>(P, S, idx, 0, nsteps, SROT_ELS, tj, tg, ta, st);
+    return launch_screened_var<1>(P, S, idx, 0, nsteps, SROT_ELS, tj, tg, ta, st);
 }
 
 }  // namespace srot

@@ -272,6 +272,9 @@ hipError_t launch_active_steps(const ProblemView &P, const DeviceState &S, int p
                                hipStream_t stream)
 {
     if (nsteps <= 0) return hipSuccess;
+    // stored FP32 cost of 513-4096 columns: the screened chain's stepper
+    if (S.screen_err > 0.0 && screened_chain_supported(P, S))
+        return launch_active_screened(P, S, pairwise, idx, nsteps, trace_j, trace_away, trace_gamma, stream);
     switch (P.cost) {
     case SROT_COST_F32:
         return pairwise ? launch_active_cost<SROT_COST_F32, 1>(P, S, idx, nsteps, trace_j, trace_away, trace_gamma, stream)

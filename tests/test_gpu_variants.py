@@ -145,6 +145,7 @@ def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
     ("stored", np.float32, 60, 300, 0.5),
     ("sqeuclid", None, 40, 77, 2.0),
     ("stored", np.float64, 24, 5000, 1.0),
+    ("stored", np.float32, 40, 1000, 1.0),       # the screened chain's stepper (513-4096 columns)
 ])
 def test_every_step_from_the_gpu_state(variant, cost_mode, dtype, m, n, w):
     """The oracle takes each step from the GPU's own state (plan and
@@ -191,10 +192,11 @@ def test_every_step_from_the_gpu_state(variant, cost_mode, dtype, m, n, w):
 
 
 @pytest.mark.parametrize("variant", [1, 2])
-def test_variants_converge_to_the_optimum(variant):
+@pytest.mark.parametrize("dtype,n", [(np.float64, 50), (np.float32, 600)])   # FP32 600: the screened chain
+def test_variants_converge_to_the_optimum(variant, dtype, n):
     S = _S()
-    m, n, w = 40, 50, 1.0
-    d = I.problem_mixture(15, m, n, cost_dtype=np.float64)
+    m, w = 40, 1.0
+    d = I.problem_mixture(15, m, n, cost_dtype=dtype)
     sol, P = _pair(d, "stored", w, eps=1e-9, max_passes=20000, seed=1)
     st, (g, f, D), passes = S.srot_solve_variant(sol.h, variant)
     sol.close()
@@ -207,14 +209,16 @@ def test_variants_converge_to_the_optimum(variant):
     assert abs(f - ref["f"]) <= g + ref["g"] + 1e-15       # both within their gaps of f*
 
 
-@pytest.mark.parametrize("variant,gap_every,max_passes", [(1, 1, 400), (2, 2, 400), (1, 1, 11)])
-def test_solve_variant_leaves_the_state_of_its_stopping_pass(variant, gap_every, max_passes):
+@pytest.mark.parametrize("variant,gap_every,max_passes,n,dtype", [
+    (1, 1, 400, 90, np.float64), (2, 2, 400, 90, np.float64), (1, 1, 11, 90, np.float64),
+    (2, 1, 400, 700, np.float32)])                                   # FP32 700: the screened chain
+def test_solve_variant_leaves_the_state_of_its_stopping_pass(variant, gap_every, max_passes, n, dtype):
     """The stop test runs on the device with passes queued ahead: the plan
     and residual left are those of the stopping pass (as stepping that many
     passes by hand) and (g, f, D) is the sweep of that state."""
     S = _S()
-    m, n = 60, 90
-    d = I.problem_mixture(16, m, n, cost_dtype=np.float64)
+    m = 60
+    d = I.problem_mixture(16, m, n, cost_dtype=dtype)
     opts = dict(eps=1e-7, max_passes=max_passes, gap_every=gap_every, seed=3)
     sol, _ = _pair(d, "stored", 1.0, **opts)
     ref, _ = _pair(d, "stored", 1.0, **opts)
