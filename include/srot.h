@@ -265,6 +265,9 @@ int srot_backward_noalloc(srot_handle *h, double grad_out, void *dC, float *dX, 
  *   (eq. SemiRelaxedBCAFWStep); reaching gamma_max on an away or pairwise
  *   direction empties atom ja exactly.
  * Needs opt->step_rule == SROT_ELS and rows of at most 8192 columns.
+ * Stored FP32 rows of 513-4096 columns take the steps on the screened LMO
+ * chain of srot_step (SROT_CHAIN_SCREENED): the same steps, with the support
+ * sums added in another order.
  *   idx          device block indices, or NULL for the handle's sampler.
  *   trace_j      device int32 per step (optional): js.
  *   trace_away   device int32 per step (optional): ja, or -1 - ja when the
