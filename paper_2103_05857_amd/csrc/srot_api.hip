@@ -660,9 +660,9 @@ int srot_fw_steps(srot_handle *h, int64_t iters, double *trace_gamma)
 }
 
 // Iterations are queued in batches; each sweep checks the device's done
-// flag, and the host reads the run state of batch b (copied to pinned
-// memory behind it) only after batch b + 1 is queued, so the GPU does not
-// wait for the host between batches.
+// flag, and the host reads the run state of batch b (written to pinned
+// memory by the batch's last step kernel) only after batch b + 1 is queued,
+// so the GPU does not wait for the host between batches.
 constexpr int64_t kFwBatch = 4;
 
 int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters)
@@ -675,15 +675,18 @@ int srot_fw_solve(srot_handle *h, double *out3, int64_t *iters)
     SROT_HIP(srot::launch_fw_reset(h->P, h->S, h->stream));
     // sweeps i0 .. i1 - 1 and the readback of the run state into slot q; the
     // sweep numbered maxit only measures
+    // (the batch's last step kernel writes the run state and the sums into
+    // the pinned slot itself: no copy per batch)
     auto queue = [&](int64_t i0, int64_t i1, int q) -> int {
         for (int64_t it = i0; it < i1; ++it) {
-            const srot::FwSweep f = srot::fw_sweep_args(h->S, h->opt.eps, h->opt.step_rule, it < maxit ? 1 : 0,
-                                                        h->fw_k + it, nullptr);
+            srot::FwSweep f = srot::fw_sweep_args(h->S, h->opt.eps, h->opt.step_rule, it < maxit ? 1 : 0,
+                                                  h->fw_k + it, nullptr);
+            if (it == i1 - 1) {
+                f.rb_words = h->rb[q].words;
+                f.rb_sums = h->rb[q].sums;
+            }
             SROT_HIP(srot::launch_fw_iteration(h->P, h->S, f, h->stream));
         }
-        SROT_HIP(hipMemcpyAsync(h->rb[q].words, h->S.flags + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                h->stream));
-        SROT_HIP(hipMemcpyAsync(h->rb[q].sums, h->S.scalars, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         SROT_HIP(hipEventRecord(h->rb_ev[q], h->stream));
         return SROT_OK;
     };

@@ -88,6 +88,8 @@ struct FwStepArgs {
     int32_t rule, allow_step;
     int64_t k;
     double *trace_gamma;
+    int32_t *rb_words;  // pinned host memory (the run's readback slot), or null
+    double *rb_sums;
 };
 
 int fw_dd_blocks(int32_t n) { return (int)std::min<int64_t>(((int64_t)n + FW_DD_COLS - 1) / FW_DD_COLS, FW_DD_MAX_BLOCKS); }
@@ -208,6 +210,15 @@ __global__ __launch_bounds__(FW_STEP_NT) void fw_update_kernel(int32_t n, double
                 state[1] = 0;
                 if (g <= A.eps) state[0] = 1;
             }
+            // the run state and the sums straight into the host's readback
+            // slot (visible to the host once the launch has completed)
+            if (A.rb_words) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    A.rb_words[c] = state[c];
+                    A.rb_sums[c] = scal[c];
+                }
+            }
         }
         s_stop = stop;
         s_gam = gamma;
@@ -265,6 +276,8 @@ hipError_t launch_fw_iteration(const ProblemView &P, const DeviceState &S, const
     A.allow_step = fw.allow_step;
     A.k = fw.k;
     A.trace_gamma = fw.trace_gamma;
+    A.rb_words = fw.rb_words;
+    A.rb_sums = fw.rb_sums;
     if (P.n <= FW_SELF_COLS) {
         // one workgroup holds every column: ||d||^2 and the update in one launch
         hipLaunchKernelGGL(fw_update_kernel<true>, dim3(1), dim3(FW_STEP_NT), 0, st, P.n, P.w, P.b, S.r, fw.s_fixed,

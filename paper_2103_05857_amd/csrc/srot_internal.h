@@ -180,6 +180,8 @@ struct FwSweep {
     int32_t allow_step;             // 0: measure only
     int64_t k;                      // FW iteration counter (decay rule 2/(k+2))
     double *trace_gamma;            // device, one entry, or null
+    int32_t *rb_words;              // pinned host memory, or null: the run state [0..2] after the step
+    double *rb_sums;                // pinned host memory, or null: g, f, D of the sweep
 };
 // The sweep alone (its nb workgroup partials are left for gap_total).
 hipError_t launch_gap_fw(const ProblemView &P, const DeviceState &S, const FwSweep &fw, hipStream_t stream, int *nb);
@@ -204,6 +206,8 @@ inline FwSweep fw_sweep_args(const DeviceState &S, double eps, int rule, int all
     f.allow_step = allow_step;
     f.k = k;
     f.trace_gamma = trace_gamma;
+    f.rb_words = nullptr;
+    f.rb_sums = nullptr;
     return f;
 }
 
