@@ -191,7 +191,7 @@ def main():
     nnz = float(np.mean(nnz_rows))
     bytes_per_step = 4.0 * n + 24.0 * (nnz + 1.0)
     achieved = bytes_per_step * m / (chain_avg_ms * 1e-3) / 1e9
-    traffic = counter_traffic("srot::chain_screened_kernel<16, false>")
+    traffic = counter_traffic("srot::chain_screened_kernel<16, false, 0>")
     roofline = dict(kernel="chain_screened_kernel<16,f32>", bound="hbm", achieved=achieved,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, bytes_per_launch=bytes_per_step * m, launch_ms=chain_avg_ms,
