@@ -47,6 +47,24 @@ __device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
            (uint32_t)__builtin_amdgcn_readlane((int)v, 32) | (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
+// Inclusive sum of x over the wave in lane order: log-step adds of the row
+// shifts by 1, 2, 4, 8 within each row of 16 lanes (DPP; lanes with no
+// source read 0), then each row adds the totals of the rows before it, in
+// row order.  *prev gets the sum of the lanes below (0 in lane 0).
+__device__ __forceinline__ double wave_incl_scan(double x, double *prev)
+{
+    x += dpp_f64<0x111>(x);  // row_shr:1
+    x += dpp_f64<0x112>(x);  // row_shr:2
+    x += dpp_f64<0x114>(x);  // row_shr:4
+    x += dpp_f64<0x118>(x);  // row_shr:8
+    const double r0 = readlane_f64(x, 15), r1 = readlane_f64(x, 31), r2 = readlane_f64(x, 47);
+    const double o1 = r0, o2 = o1 + r1, o3 = o2 + r2;
+    const int row = (threadIdx.x & 63) >> 4;
+    x = row == 0 ? x : x + (row == 1 ? o1 : (row == 2 ? o2 : o3));
+    *prev = dpp_f64<0x138>(x);  // wave_shr:1
+    return x;
+}
+
 // Uniform double in [0, 1) from output k of the block-index stream.
 __device__ __forceinline__ double philox_unit(uint64_t seed, int64_t k)
 {
@@ -98,19 +116,17 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
         r[u] = (j < n) ? rg[j] : 0.0;
     }
 
+    // the uniform of each step is formed during the step before (while
+    // that step's row is in flight)
+    double u_next = nsteps > 0 ? (u_in ? u_in[0] : philox_unit(seed, k0)) : 0.0;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)(s & 1);
-        double u = u_in ? u_in[s] : philox_unit(seed, k0 + s);
+        double u = u_next;
         u = (u >= 0.0 && u < 1.0) ? u : 0.0;
 
         // ---- draw i with probability W_i / sum W ----
-        double inc = cs;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double y = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += y;
-        }
-        const double below = __shfl_up(inc, 1, 64);
+        double below;
+        const double inc = wave_incl_scan(cs, &below);
         if (lane == 63) s_tot[par][wid] = inc;
         __syncthreads();
         double run = 0.0, off = 0.0;
@@ -186,6 +202,7 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
             const int j = owned_col<NT, VEC>(u2, tid);
             tl[u2] = T[base + (j < n ? j : n - 1)];
         }
+        if (s + 1 < nsteps) u_next = u_in ? u_in[s + 1] : philox_unit(seed, k0 + s + 1);
         double best = INFINITY;
         int bj = 0x7fffffff;
 #pragma unroll
