@@ -15,9 +15,9 @@
 //     every thread knows its chunk's upper end and the total;
 //   * the drawn chunk is the lowest thread with a positive sum whose upper
 //     end exceeds x (or, should rounding leave none, the last positive one),
-//     and its owner walks its rows from the chunk's lower end to the first
+//     and its wave walks its rows from the chunk's lower end to the first
 //     positive weight whose running end exceeds x (else its last positive
-//     weight).
+//     weight), 64 rows at a time with the running ends from a wave scan.
 // This is inversion of W / sum W with sums formed in another order than a
 // plain running sum, so a draw can differ from one made with a running sum
 // only where x lies within rounding of an interval end.  A block with zero
@@ -149,29 +149,27 @@ __global__ __launch_bounds__(NT) void ga_step_kernel(ProblemView P, double *__re
             const unsigned long long pb = __ballot(cs > 0.0);
             int cand = -1;
             if (fb) {
+                // the chunk of the wave's first lane with hi > x, walked by
+                // the whole wave 64 rows at a time: each lane takes one row,
+                // the running ends come from a wave scan added to the
+                // chunk's lower end; the first positive weight whose end
+                // exceeds x, else the chunk's last positive weight
                 const int fl = __ffsll((long long)fb) - 1;
-                if (lane == fl) {
-                    // the running sum in row order over the chunk, its
-                    // entries read eight at a time
-                    double c = lo;
-                    int lp = -1;
-                    for (int q8 = q0; q8 < q1 && cand < 0; q8 += 8) {
-                        double wv[8];
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) wv[e] = (q8 + e < q1) ? s_W[q8 + e] : 0.0;
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const double wq = wv[e];
-                            if (cand < 0 && wq > 0.0) {
-                                lp = q8 + e;
-                                c += wq;
-                                if (c > x) cand = q8 + e;
-                            }
-                        }
-                    }
-                    if (cand < 0) cand = lp;
+                const int q0f = min(m, (wid * 64 + fl) * L), q1f = min(m, q0f + L);
+                double base = readlane_f64(lo, fl);
+                int lp = -1;
+                for (int qb = q0f; qb < q1f && cand < 0; qb += 64) {  // uniform over the wave
+                    const int q = qb + lane;
+                    const double wq = q < q1f ? s_W[q] : 0.0;
+                    double prev;
+                    const double end = base + wave_incl_scan(wq, &prev);
+                    const unsigned long long hit = __ballot(wq > 0.0 && end > x);
+                    const unsigned long long pos = __ballot(wq > 0.0);
+                    if (hit) cand = qb + __ffsll((long long)hit) - 1;
+                    if (pos) lp = qb + 63 - __clzll((long long)pos);
+                    base = readlane_f64(end, 63);
                 }
-                cand = __builtin_amdgcn_readlane(cand, fl);
+                if (cand < 0) cand = lp;
             }
             int lastw = -1;
             if (pb) lastw = __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)pb));
