@@ -159,6 +159,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
         double dec[SC_DECN];
 #pragma unroll
         for (int k = 0; k < SC_DECN; ++k) dec[k] = 0.0;
+        double wds = 0.0;  // w times the sum of dec, formed at the end of the step before
         int64_t n_fall = 0, n_slow = 0;
 
         for (int64_t p = -LAG_A; p < nsteps; ++p) {
@@ -233,10 +234,7 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 // LMO over the candidates, accepted against the screen's bound
                 const double vc = cj >= 0 ? (double)cc + w * rc : INFINITY;
                 double vstar = wave_min(vc);
-                double dsum = 0.0;
-#pragma unroll
-                for (int k = 0; k < SC_DECN; ++k) dsum += dec[k];
-                const double bound = (double)tau - err - w * dsum;
+                const double bound = (double)tau - err - wds;
                 int jstar;
                 bool fell = false;
                 if (vstar < bound) {
@@ -527,6 +525,12 @@ __global__ __launch_bounds__(SC_NT) void chain_screened_kernel(ProblemView P, do
                 // largest entry off the FW vertex, or t_ija on an away or
                 // pairwise direction
                 dec[0] = fw_dir ? gamma * smax : sta;
+                {
+                    double dsum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < SC_DECN; ++k) dsum += dec[k];
+                    wds = w * dsum;
+                }
                 // every store of earlier steps is complete before the barrier
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(NST));
             }
