@@ -55,6 +55,12 @@ def _run_gpu(sol, variant, idx):
     return tj.cpu().numpy(), ta.cpu().numpy(), tg.cpu().numpy()
 
 
+def _screened(cost_mode, dtype, n):
+    """Stored FP32 rows of 513-4096 columns (a multiple of 4): the steps run
+    on the screened chain's stepper."""
+    return cost_mode == "stored" and dtype == np.float32 and 513 <= n <= 4096 and n % 4 == 0
+
+
 def _first_divergence(otr, gj, ga, gg, sizes_may_differ=False):
     """Index of the first step where the GPU and the oracle differ (len(gj)
     if none), after checking that the difference is allowed.  With
@@ -126,6 +132,8 @@ def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
         pos += k + 1
         ties += 1
     assert ties <= 0.05 * len(idx), ties
+    if _screened(cost_mode, dtype, n):
+        assert _S().srot_chain_stats(sol.h)[2] == _S().SROT_CHAIN_SCREENED
     T, r = sol.plan()
     T = T.cpu().numpy()
     np.testing.assert_allclose(T, st.T, rtol=0, atol=1e-9)
@@ -188,6 +196,8 @@ def test_every_step_from_the_gpu_state(variant, cost_mode, dtype, m, n, w):
             assert abs(gg[0] - otr["gamma"][0]) <= 1e-9, (k, gg[0], otr["gamma"][0])
         checked += 1
     assert checked >= 0.8 * len(idx)
+    if _screened(cost_mode, dtype, n):
+        assert S.srot_chain_stats(sol.h)[2] == S.SROT_CHAIN_SCREENED   # the screened kernel took the steps
     sol.close()
 
 
