@@ -108,13 +108,14 @@ def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
     sol, P = _pair(d, cost_mode, w)
     idx = I.philox_uniform_indices(5, 0, 6 * m, m)
     ovar = O.PAIRWISE if variant == 2 else O.AWAY
-    pos, ties = 0, 0
+    pos, ties, slow = 0, 0, 0
     while True:
         T0, r0 = sol.plan()
         st = O.State(P, T0.cpu().numpy())
         st.r = r0.cpu().numpy().copy()
         otr = O.active_steps(P, st, idx[pos:], ovar)
         gj, ga, gg = _run_gpu(sol, variant, idx[pos:])
+        slow += _S().srot_chain_stats(sol.h)[1]
         k = _first_divergence(otr, gj, ga, gg, sizes_may_differ=True)
         if k == len(idx) - pos:
             break
@@ -134,6 +135,9 @@ def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
     assert ties <= 0.05 * len(idx), ties
     if _screened(cost_mode, dtype, n):
         assert _S().srot_chain_stats(sol.h)[2] == _S().SROT_CHAIN_SCREENED
+        # rows revisited within the stepper's history were re-read from the
+        # plan (about 3% of the steps here)
+        assert slow > 0
     T, r = sol.plan()
     T = T.cpu().numpy()
     np.testing.assert_allclose(T, st.T, rtol=0, atol=1e-9)
@@ -154,6 +158,7 @@ def test_variant_traces_match_oracle(variant, cost_mode, dtype, m, n, w):
     ("sqeuclid", None, 40, 77, 2.0),
     ("stored", np.float64, 24, 5000, 1.0),
     ("stored", np.float32, 40, 1000, 1.0),       # the screened chain's stepper (513-4096 columns)
+    ("stored", np.float32, 24, 700, 10.0),       # wider supports at a large penalty
 ])
 def test_every_step_from_the_gpu_state(variant, cost_mode, dtype, m, n, w):
     """The oracle takes each step from the GPU's own state (plan and
