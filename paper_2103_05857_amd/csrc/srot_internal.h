@@ -159,18 +159,19 @@ int32_t adjoint_slices_cap(int64_t m);
 // doubles of per-slice dY column sums (adj_part) that launch_adjoint uses
 size_t adjoint_part_doubles(const ProblemView &P, const Ownership &own);
 
-// Full Frank-Wolfe (Alg. A.1) as two launches per iteration.  The sweep of
+// Full Frank-Wolfe (Alg. A.1): per iteration the sweep and the step (one
+// launch up to 4096 columns, two beyond).  The sweep of
 // iteration k first applies the step of iteration k - 1 to each row as it
 // reaches it (t_i <- (1 - gamma) t_i + gamma a_i e_{j*_i}, gamma in
 // scalars[5], j*_i in row_j), then measures the row's vertex and gap at the
 // new plan and adds a_i to the vertex column sum s = S^T 1 (fixed point,
 // device-scope integer atomics: order-free, so the sums are reproducible).
-// The step kernel (srot_fw.hip) then either stops (gap <= eps, or a
+// The step (srot_fw.hip) then either stops (gap <= eps, or a
 // measuring-only sweep) or takes the line search on d = r + b - s, writes
 // gamma and the new residual r <- (1 - gamma)(r + b) + gamma s - b, and
-// leaves the row updates pending for the next sweep.  Launches that find
-// the done flag set return at once, so the host can queue iterations and
-// read the flag once per batch.
+// leaves the row updates pending for the next sweep.  Once the done flag
+// is set the sweep returns at once and the step takes the same stop again,
+// so the host can queue iterations and read the flag once per batch.
 struct FwSweep {
     int32_t *state;                 // [0] done, [1] a step is pending, [2] steps taken
     unsigned long long *s_fixed;    // n vertex column sums, zero between sweeps
