@@ -47,6 +47,8 @@ def _oracle(d, cost_mode, w):
     ("sqeuclid", None, 200, 333, 2.0, 1),
     ("stored", np.float32, 41, 5000, 1.0, 0),       # wide-row ownership
     ("sqeuclid", None, 19, 9000, 1.0, 0),           # wide fused rows
+    ("stored", np.float32, 3, 70000, 1.0, 0),       # the update kernel's workgroups loop over the columns
+    ("stored", np.float32, 2, 270000, 1.0, 1),      # and so do the ||d||^2 kernel's
 ])
 def test_fw_iterations_match_oracle(cost_mode, dtype, m, n, w, rule):
     S = _S()
