@@ -95,6 +95,7 @@ def _first_divergence(otr, gj, ga, gg, sizes_may_differ=False):
     ("stored", np.float32, 300, 700, 0.5),
     ("sqeuclid", None, 200, 333, 2.0),
     ("stored", np.float32, 97, 4096, 1.0),
+    ("stored", np.float32, 50, 1500, 1.0),         # the screened chain with 8 columns per owner thread
     ("stored", np.float32, 40, 6000, 1.0),         # wide rows: 512 threads x 12 columns
     ("sqeuclid", None, 30, 8192, 1.0),
 ])
