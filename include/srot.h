@@ -46,6 +46,7 @@ extern "C" {
 #define SROT_ENOMEM         -2   /* workspace smaller than srot_workspace_size */
 #define SROT_ENONFINITE     -3   /* NaN/Inf or negative weight in the inputs  */
 #define SROT_EHIP           -4   /* a HIP runtime call failed                  */
+#define SROT_ECAPACITY      -5   /* an output buffer holds fewer entries than needed */
 
 /* step rules (Alg. 1, Sec. 3.1) */
 #define SROT_ELS  0   /* exact line search, eq. SemiRelaxedBCFWStep     */
@@ -161,6 +162,23 @@ int srot_solve(srot_handle *h, double *out3, int64_t *passes);
 /* Copies the dense plan T (device, m x n double) and the residual
  * r = T^T 1 - b (device, n double) out; either may be NULL. */
 int srot_get_plan(srot_handle *h, double *T_out, double *r_out);
+
+/* The plan in compressed sparse rows: row i's support (its active set,
+ * Sec. 4.1, eq. ActiveSet: the columns with t_ij > 0) in ascending column
+ * order, with the plan entries; read from the support masks, so only the
+ * support of T is touched.
+ *   row_ptr  device, m + 1 int32: row i's entries are
+ *            [row_ptr[i], row_ptr[i + 1]); always written.
+ *   col      device, cap int32 column indices, or NULL with cap = 0.
+ *   val      device, cap double plan entries, or NULL with cap = 0.
+ *   cap      entries col and val can hold (>= 0).
+ *   nnz      host: the number of entries, also when it exceeds cap.
+ * col and val are written only when nnz <= cap, on the handle's stream
+ * (asynchronously); reading the count synchronises.
+ * Errors: SROT_EINVAL (NULL h, row_ptr or nnz, cap < 0, col or val NULL
+ * with cap > 0, more than 2^31 - 1 entries), SROT_ECAPACITY (nnz > cap:
+ * call again with a larger buffer), SROT_EHIP. */
+int srot_get_plan_csr(srot_handle *h, int32_t *row_ptr, int32_t *col, double *val, int64_t cap, int64_t *nnz);
 
 /* Checkpoint / resume: the state is (T, r, k).  srot_get_state writes the
  * block-step counter to *k (host); srot_get_plan copies T and r.

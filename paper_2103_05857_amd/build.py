@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrot.so")
 CALIB = os.path.join(HERE, "copy_calibrate")
-SOURCES = ["srot_kernels.hip", "srot_adjoint.hip", "srot_batched.hip", "srot_fw.hip", "srot_variants.hip", "srot_ga.hip", "srot_screen.hip", "srot_team.hip", "srot_api.hip"]
+SOURCES = ["srot_kernels.hip", "srot_adjoint.hip", "srot_batched.hip", "srot_fw.hip", "srot_variants.hip",
+           "srot_ga.hip", "srot_screen.hip", "srot_team.hip", "srot_plan.hip", "srot_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

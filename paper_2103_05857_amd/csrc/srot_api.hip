@@ -558,6 +558,24 @@ int srot_get_plan(srot_handle *h, double *T_out, double *r_out)
     return SROT_OK;
 }
 
+int srot_get_plan_csr(srot_handle *h, int32_t *row_ptr, int32_t *col, double *val, int64_t cap, int64_t *nnz)
+{
+    if (!h || !row_ptr || !nnz) return fail(SROT_EINVAL, "srot_get_plan_csr: NULL argument");
+    if (cap < 0) return fail(SROT_EINVAL, "srot_get_plan_csr: cap < 0");
+    if (cap > 0 && (!col || !val)) return fail(SROT_EINVAL, "srot_get_plan_csr: col or val NULL with cap > 0");
+    *nnz = 0;
+    SROT_HIP(srot::launch_plan_count(h->P, h->S, row_ptr, h->stream));
+    int32_t total = 0;
+    SROT_HIP(hipMemcpyAsync(&total, row_ptr + h->P.m, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    SROT_HIP(hipStreamSynchronize(h->stream));
+    if (total < 0) return fail(SROT_EINVAL, "srot_get_plan_csr: more than 2^31 - 1 plan entries");
+    *nnz = total;
+    if (total > cap)
+        return fail(SROT_ECAPACITY, "srot_get_plan_csr: %d entries, the buffers hold %lld", total, (long long)cap);
+    if (total > 0) SROT_HIP(srot::launch_plan_fill(h->P, h->S, row_ptr, col, val, h->stream));
+    return SROT_OK;
+}
+
 int srot_get_state(srot_handle *h, int64_t *k)
 {
     if (!h || !k) return fail(SROT_EINVAL, "srot_get_state: NULL argument");
@@ -845,6 +863,7 @@ const char *srot_strerror(int status)
     case SROT_ENOMEM: return "workspace too small";
     case SROT_ENONFINITE: return "non-finite or negative input";
     case SROT_EHIP: return "HIP runtime error";
+    case SROT_ECAPACITY: return "output buffer too small";
     default: return "unknown status";
     }
 }

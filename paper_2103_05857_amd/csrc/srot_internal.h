@@ -193,6 +193,13 @@ hipError_t launch_fw_iteration(const ProblemView &P, const DeviceState &S, const
 hipError_t launch_fw_reset(const ProblemView &P, const DeviceState &S, hipStream_t stream);
 // After a run: applies a pending step to every row (srot_fw.hip).
 hipError_t launch_fw_flush(const ProblemView &P, const DeviceState &S, hipStream_t stream);
+
+// The plan in compressed sparse rows (srot_plan.hip): row counts from the
+// support masks scanned into row_ptr (m + 1 entries; -1 from the first
+// offset past 2^31 - 1 on), then each row's columns and entries.
+hipError_t launch_plan_count(const ProblemView &P, const DeviceState &S, int32_t *row_ptr, hipStream_t stream);
+hipError_t launch_plan_fill(const ProblemView &P, const DeviceState &S, const int32_t *row_ptr, int32_t *col,
+                            double *val, hipStream_t stream);
 // Device words of the FW run state inside DeviceState (flags[1..3]) and the
 // scale (scalars[7]); s lives in adj_part.
 inline FwSweep fw_sweep_args(const DeviceState &S, double eps, int rule, int allow_step, int64_t k,

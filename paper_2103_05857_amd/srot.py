@@ -20,6 +20,7 @@ SROT_EINVAL = -1
 SROT_ENOMEM = -2
 SROT_ENONFINITE = -3
 SROT_EHIP = -4
+SROT_ECAPACITY = -5
 
 SROT_ELS = 0
 SROT_DEC = 1
@@ -82,6 +83,8 @@ def load():
     L.srot_solve.restype = ctypes.c_int
     L.srot_get_plan.argtypes = [_vp, _vp, _vp]
     L.srot_get_plan.restype = ctypes.c_int
+    L.srot_get_plan_csr.argtypes = [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]
+    L.srot_get_plan_csr.restype = ctypes.c_int
     L.srot_get_state.argtypes = [_vp, ctypes.POINTER(_i64)]
     L.srot_get_state.restype = ctypes.c_int
     L.srot_set_state.argtypes = [_vp, _vp, _vp, _i64]
@@ -216,6 +219,20 @@ def srot_solve(h):
 
 def srot_get_plan(h, T_out=None, r_out=None):
     _check(load().srot_get_plan(h, _ptr(T_out, _F64), _ptr(r_out, _F64)))
+
+
+def srot_get_plan_csr(h, row_ptr, col=None, val=None):
+    """Writes the plan's compressed sparse rows into row_ptr (m + 1 int32)
+    and, when they hold enough entries, col (int32) and val (float64);
+    returns the number of entries (SrotError with status SROT_ECAPACITY when
+    col and val are too small; without them it only counts)."""
+    count_only = col is None or val is None
+    cap = 0 if count_only else min(col.numel(), val.numel())
+    nnz = _i64()
+    _check(load().srot_get_plan_csr(h, _ptr(row_ptr, _I32, 1), None if count_only else _ptr(col, _I32),
+                                    None if count_only else _ptr(val, _F64), cap, ctypes.byref(nnz)),
+           allow=(SROT_OK, SROT_ECAPACITY) if count_only else (SROT_OK,))
+    return nnz.value
 
 
 def srot_get_state(h):
@@ -456,6 +473,17 @@ class Solver:
         r = torch.empty(self.n, dtype=torch.float64, device=self.workspace.device)
         srot_get_plan(self.h, T, r)
         return T, r
+
+    def plan_csr(self):
+        """The plan's support as (row_ptr, col, val) CUDA tensors."""
+        dev = self.workspace.device
+        row_ptr = torch.empty(self.m + 1, dtype=torch.int32, device=dev)
+        nnz = srot_get_plan_csr(self.h, row_ptr)
+        col = torch.empty(nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(nnz, dtype=torch.float64, device=dev)
+        if nnz:
+            srot_get_plan_csr(self.h, row_ptr, col, val)
+        return row_ptr, col, val
 
     @property
     def k(self):

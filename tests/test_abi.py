@@ -96,6 +96,9 @@ def test_null_handle_is_rejected():
     assert L.srot_chain_stats(None, stats) == S.SROT_EINVAL
     assert L.srot_backward(None, 1.0, None, None, None, None, None) == S.SROT_EINVAL
     assert L.srot_backward_noalloc(None, 1.0, None, None, None, None, None) == S.SROT_EINVAL
+    nnz = ctypes.c_int64()
+    assert L.srot_get_plan_csr(None, None, None, None, 0, ctypes.byref(nnz)) == S.SROT_EINVAL
+    assert L.srot_strerror(S.SROT_ECAPACITY) == b"output buffer too small"
     assert L.srot_strerror(S.SROT_ENONFINITE) == b"non-finite or negative input"
 
 
