@@ -33,6 +33,7 @@ def _solver(d, cost_mode, w):
     ("stored", np.float32, 40, 5000, 1.0, 5),        # rows of several mask words per thread
     ("sqeuclid", None, 30, 20000, 0.5, 3),           # the team chain's layout
     ("stored", np.float32, 1, 7, 1.0, 0),            # one row, the initial plan
+    ("stored", np.float64, 20000, 16, 1.0, 1),       # rows beyond one launch's waves, 20 per scan thread
 ])
 def test_csr_plan_matches_the_dense_plan(cost_mode, dtype, m, n, w, passes):
     S = _S()
